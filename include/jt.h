@@ -1,0 +1,202 @@
+/*
+ * jt.h -- C ABI of the MI355X junction-tree message engine.
+ *
+ * The engine computes junction-tree belief propagation (Zheng, Mengshoel,
+ * Chong, "Belief Propagation by Message Passing in Junction Trees: Computing
+ * Each Message Faster Using GPU Parallelization"): every message is the
+ * marginalization of a clique table into a separator (eq. (2)), the new/old
+ * separator ratio with 0/0 := 0, and the scatter-multiply of that ratio into
+ * the neighbouring clique (eq. (3)), driven over the collect and distribute
+ * sweeps of Algorithms 2-4.  The cluster-separator index mappings of
+ * Sec. 3.1-3.2 are precomputed once, when the tree is compiled.
+ *
+ * Conventions
+ *   - Variables are 0..n_vars-1, variable v has card[v] >= 1 states.
+ *   - Clique c lists its variables in clique_vars[clique_off[c] ..
+ *     clique_off[c+1]).  The listed order is the table layout: row-major,
+ *     last-listed variable fastest.  |phi_X| = product of the cardinalities
+ *     (Sec. 3) and must be below 2^31.
+ *   - parent[c] is the neighbour towards the root; exactly one clique has
+ *     parent -1 (the designated root of Sec. 2.1).  The separator of edge
+ *     (c, parent[c]) is the intersection of the two variable sets, ordered by
+ *     ascending variable id; separator tables are row-major in that order.
+ *   - Potentials are FP32.  Messages are scaled: every new separator table
+ *     is rescaled to mean one and the log of the scale is carried in FP64,
+ *     so log P(evidence) (more precisely log Z_e, the log of the
+ *     evidence-restricted partition function) is exact up to FP32 rounding.
+ *   - Evidence is hard: observing variable v in state s zeroes every entry
+ *     with x_v != s of the lowest-id clique that contains v.
+ *   - n_slots evidence sets ("slots") are propagated together over the same
+ *     tree (one query per slot).
+ *
+ * Memory and threads
+ *   - The library never allocates device memory.  jt_compile_index_maps
+ *     reports the device workspace size; the caller allocates it (e.g. a
+ *     torch uint8 tensor) and hands it to jt_bind.  It must stay valid until
+ *     jt_free.  Host arrays passed to any call are copied before it returns.
+ *   - A handle is bound to one HIP stream and is not thread-safe.  Distinct
+ *     handles are independent.
+ *
+ * Errors
+ *   Every call returns a jt_status: JT_OK (0) or a negative code.  No C++
+ *   exception crosses the ABI.  jt_last_error() returns a thread-local
+ *   message describing the last failure on the calling thread.
+ */
+#ifndef JT_H
+#define JT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t jt_status;
+
+#define JT_OK 0
+#define JT_E_ARG (-1)               /* bad pointer, index, slot, variable or state; conflicting evidence */
+#define JT_E_NOT_JUNCTION_TREE (-2) /* not one root, a cycle, or running intersection violated */
+#define JT_E_TOO_LARGE (-3)         /* a table with 2^31 or more entries */
+#define JT_E_NO_MEM (-4)            /* workspace smaller than required, or host allocation failed */
+#define JT_E_HIP (-5)               /* a HIP runtime error (message in jt_last_error) */
+#define JT_E_ZERO_EVIDENCE (-6)     /* P(evidence) = 0 for the slot: no posterior exists */
+#define JT_E_STATE (-7)             /* call out of order (e.g. propagate before bind) */
+
+/* Propagation schedules (all compute the same messages):
+ *   JT_MODE_FUSED  level-scheduled: all cliques of one tree level in one
+ *                  launch, marginalize and scatter fused per clique;
+ *   JT_MODE_GRAPH  the same launches replayed from one captured HIP graph;
+ *   JT_MODE_PLAIN  one message at a time in the paper's depth-first order
+ *                  (Algorithms 2-3): marginalize, ratio, scatter launches per
+ *                  message, tables updated in place. */
+#define JT_MODE_FUSED 0
+#define JT_MODE_GRAPH 1
+#define JT_MODE_PLAIN 2
+
+typedef struct jt_tree_s *jt_tree;
+
+typedef struct {
+    int32_t n_vars;
+    const int32_t *card;        /* [n_vars], each >= 1 */
+    int32_t n_cliques;
+    const int64_t *clique_off;  /* [n_cliques + 1], clique_off[0] = 0 */
+    const int32_t *clique_vars; /* [clique_off[n_cliques]], no repeats within a clique */
+    const int32_t *parent;      /* [n_cliques], exactly one -1 */
+    int32_t n_slots;            /* evidence sets propagated together, >= 1 */
+} jt_tree_desc;
+
+/* Validate the tree and precompute every cluster-separator index mapping
+ * (Sec. 3.2: the mapping tables are built once, when the junction tree is
+ * established).  Host only; touches no GPU.
+ *   desc          tree description (host arrays, copied);
+ *   out           receives the new handle (caller frees with jt_free);
+ *   device_bytes  receives the workspace size jt_bind needs.
+ * Errors: JT_E_ARG, JT_E_NOT_JUNCTION_TREE, JT_E_TOO_LARGE, JT_E_NO_MEM. */
+jt_status jt_compile_index_maps(const jt_tree_desc *desc, jt_tree *out, size_t *device_bytes);
+
+/* Attach device memory and the initial potentials, and upload the index
+ * metadata (Initialization of Algorithm 4 takes the tables from here).
+ *   workspace        device pointer, >= device_bytes bytes, 256-byte aligned;
+ *   bytes            its size;
+ *   init_potentials  device pointer to the FP32 tables concatenated in clique
+ *                    order (sum of |phi_X| floats); copied into the
+ *                    workspace, so the caller may release it afterwards;
+ *   hip_stream       hipStream_t all later work of this handle runs on
+ *                    (NULL = the default stream).
+ * Enqueues copies on the stream and returns; errors: JT_E_ARG, JT_E_NO_MEM,
+ * JT_E_HIP. */
+jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_potentials,
+                  void *hip_stream);
+
+/* Replace the evidence of one slot by n_obs hard observations (Sec. 2.1:
+ * evidence is a set of instantiated variables).  n_obs = 0 clears it.
+ *   vars, states  host arrays of n_obs entries; a variable may repeat only
+ *                 with the same state.
+ * Takes effect at the next jt_propagate.  Errors: JT_E_ARG. */
+jt_status jt_set_evidence(jt_tree t, int32_t slot, int32_t n_obs, const int32_t *vars,
+                          const int32_t *states);
+
+/* Run one full belief propagation for every slot (Algorithm 4): reset
+ * every table to the initial potentials with the slot's evidence entered,
+ * collect to the root, distribute from it.  Asynchronous on the bound
+ * stream; idempotent (always restarts from the initial potentials).
+ *   mode  JT_MODE_FUSED, JT_MODE_GRAPH or JT_MODE_PLAIN.
+ * Errors: JT_E_STATE (not bound), JT_E_ARG (mode), JT_E_HIP. */
+jt_status jt_propagate(jt_tree t, int32_t mode);
+
+/* Posterior of one clique, P(X_C | e) (Sec. 2.1: marginals are read from the
+ * calibrated tables), normalized to sum 1, and log Z_e.  Synchronizes the
+ * bound stream.
+ *   out    |phi_X| floats in the clique's table layout; host or device
+ *          pointer; may be NULL to read only log_z;
+ *   log_z  host pointer, may be NULL.
+ * Errors: JT_E_ARG, JT_E_STATE (nothing propagated yet), JT_E_HIP,
+ * JT_E_ZERO_EVIDENCE (then *log_z = -inf and out is left untouched). */
+jt_status jt_marginal(jt_tree t, int32_t slot, int32_t clique, float *out, double *log_z);
+
+/* All clique posteriors of one slot, concatenated in clique order
+ * (sum of |phi_X| floats, host or device pointer).  Same errors as
+ * jt_marginal. */
+jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z);
+
+/* The cluster-separator mapping of Sec. 3.2 in its single-table form (CSM):
+ * for edge (child, parent[child]), side 0 = the child's table, side 1 = the
+ * parent's table, host_out[r] = index of the separator entry that table
+ * entry r maps to.  host_out has |phi_X| entries.  Host only.
+ * Errors: JT_E_ARG. */
+jt_status jt_get_index_map(jt_tree t, int32_t child, int32_t side, int32_t *host_out);
+
+/* The same mapping as the paper's |phi_S| lists mu_{X, phi_S(j)}: list j
+ * holds the table entries that map to separator entry j, in ascending
+ * order, stored at host_out[j * m .. (j+1) * m) with m = |phi_X| / |phi_S|.
+ * Host only.  Errors: JT_E_ARG. */
+jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_out);
+
+/* Scalar facts about a compiled tree (host only), selected by `what`:
+ *   JT_Q_N_SLOTS, JT_Q_TOTAL_ENTRIES (sum |phi_X|),
+ *   JT_Q_TABLE_SIZE (clique = arg), JT_Q_SEP_SIZE (edge child = arg),
+ *   JT_Q_ENTRIES_PER_SWEEP (sum over the n-1 messages of one sweep of
+ *     |phi_Xi| + |phi_Xk|, eq. (4)'s numerator, per slot),
+ *   JT_Q_BYTES_FUSED (FP32 table bytes one fused propagation reads and
+ *     writes, all slots), JT_Q_BYTES_PLAIN (same for JT_MODE_PLAIN),
+ *   JT_Q_N_LAUNCHES_FUSED, JT_Q_N_LAUNCHES_PLAIN (kernel launches per
+ *     propagation), JT_Q_HEIGHT (levels of the collect sweep),
+ *   JT_Q_DEPTH (levels of the distribute sweep).
+ * Errors: JT_E_ARG. */
+#define JT_Q_N_SLOTS 0
+#define JT_Q_TOTAL_ENTRIES 1
+#define JT_Q_TABLE_SIZE 2
+#define JT_Q_SEP_SIZE 3
+#define JT_Q_ENTRIES_PER_SWEEP 4
+#define JT_Q_BYTES_FUSED 5
+#define JT_Q_BYTES_PLAIN 6
+#define JT_Q_N_LAUNCHES_FUSED 7
+#define JT_Q_N_LAUNCHES_PLAIN 8
+#define JT_Q_HEIGHT 9
+#define JT_Q_DEPTH 10
+jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
+
+/* Run one propagation with a HIP event pair around every kernel launch and
+ * report the device time spent in the streaming pass launches and in the
+ * finalize launches (milliseconds, summed over the propagation) and how many
+ * of each ran.  Synchronizes the bound stream.  For measurement only; the
+ * results it leaves are those of a normal jt_propagate.
+ *   mode  JT_MODE_FUSED or JT_MODE_PLAIN;
+ *   pass_ms, finalize_ms, n_pass, n_finalize  host pointers (any may be NULL).
+ * Errors: JT_E_STATE, JT_E_ARG, JT_E_HIP. */
+jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_ms, int32_t *n_pass,
+                     int32_t *n_finalize);
+
+/* Release the handle and its host-side objects (captured graphs included).
+ * Device memory stays the caller's.  NULL is ignored. */
+void jt_free(jt_tree t);
+
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char *jt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JT_H */

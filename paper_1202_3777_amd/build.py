@@ -1,0 +1,61 @@
+"""Build the in-tree HIP library ``libjt.so`` for gfx950.
+
+Host C++ (planner, C ABI) is compiled with g++ against the HIP runtime
+headers; the kernels are compiled with hipcc for gfx950 only.  Packed FP32
+instructions are disabled in the device code generation.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libjt.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.path.join(ROCM, "bin", "hipcc")
+ARCH = "gfx950"
+
+HOST_SRCS = ["jt_plan.cpp", "jt_api.cpp"]
+DEVICE_SRCS = ["jt_kernels.hip"]
+DEVICE_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _run(cmd):
+    subprocess.check_call(cmd)
+
+
+def sources():
+    return [os.path.join(CSRC, s) for s in HOST_SRCS + DEVICE_SRCS] + [
+        os.path.join(CSRC, "jt_internal.h"), os.path.join(CSRC, "jt_plan.h"),
+        os.path.join(ROOT, "include", "jt.h")]
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs = []
+    for s in HOST_SRCS:
+        o = os.path.join(BUILD, s.replace(".cpp", ".o"))
+        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
+              "-I", os.path.join(ROCM, "include")] + inc + ["-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    for s in DEVICE_SRCS:
+        o = os.path.join(BUILD, s.replace(".hip", ".o"))
+        _run([HIPCC] + DEVICE_FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,461 @@
+// jt_api.cpp -- the C ABI of include/jt.h: handles, binding of caller-owned
+// device memory, evidence upload, the propagation schedules (level-fused,
+// captured graph, one message at a time) and read-out.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "jt.h"
+#include "jt_plan.h"
+
+hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, hipStream_t s);
+hipError_t jt_launch_finalize(const JtDev &d, int msg_begin, int n_msgs, int n_slots, hipStream_t s);
+hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s);
+
+namespace {
+
+thread_local std::string g_err;
+
+jt_status set_err(jt_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+jt_status hip_err(hipError_t e, const char *what) {
+    return set_err(JT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct jt_tree_s {
+    jt::Plan plan;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    bool propagated = false;
+    JtDev dev;
+    std::vector<std::vector<int32_t>> ev_vars, ev_states;
+    std::vector<char> ev_dirty;
+    std::vector<int32_t> ev_idx_host;   // [n_slots][ev_idx_stride]
+    std::vector<JtEv> ev_ent_host;      // [n_slots][ev_ent_stride]
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+jt_status check_tree(jt_tree t) {
+    if (!t) return set_err(JT_E_ARG, "tree handle is NULL");
+    return JT_OK;
+}
+
+jt_status upload_evidence(jt_tree t) {
+    const jt::Plan &P = t->plan;
+    const int S = P.n_slots;
+    int lo = S, hi = -1;
+    for (int s = 0; s < S; ++s)
+        if (t->ev_dirty[s]) {
+            jt::evidence_tables(P, t->ev_vars[s], t->ev_states[s], &t->ev_idx_host[(size_t)s * P.ev_idx_stride],
+                                &t->ev_ent_host[(size_t)s * P.ev_ent_stride]);
+            t->ev_dirty[s] = 0;
+            lo = std::min(lo, s);
+            hi = std::max(hi, s);
+        }
+    if (hi < 0) return JT_OK;
+    const size_t n = (size_t)(hi - lo + 1);
+    hipError_t e = hipMemcpyAsync(t->ws + P.off_ev_idx + (size_t)lo * P.ev_idx_stride * sizeof(int32_t),
+                                  &t->ev_idx_host[(size_t)lo * P.ev_idx_stride], n * P.ev_idx_stride * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, t->stream);
+    if (e != hipSuccess) return hip_err(e, "evidence upload");
+    e = hipMemcpyAsync(t->ws + P.off_ev_ent + (size_t)lo * P.ev_ent_stride * sizeof(JtEv),
+                       &t->ev_ent_host[(size_t)lo * P.ev_ent_stride], n * P.ev_ent_stride * sizeof(JtEv),
+                       hipMemcpyHostToDevice, t->stream);
+    if (e != hipSuccess) return hip_err(e, "evidence upload");
+    return JT_OK;
+}
+
+jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L) {
+    const int S = t->plan.n_slots;
+    for (const jt::Launch &l : L) {
+        hipError_t e = hipSuccess;
+        if (l.is_pass == 2) {
+            e = jt_launch_plain_init(t->dev, S, t->stream);
+        } else if (l.count > 0) {
+            if ((int64_t)l.count * S > 0x7fffffffLL) return set_err(JT_E_TOO_LARGE, "grid too large");
+            e = l.is_pass ? jt_launch_pass(t->dev, l.begin, l.count, S, t->stream)
+                          : jt_launch_finalize(t->dev, l.begin, l.count, S, t->stream);
+        }
+        if (e != hipSuccess) return hip_err(e, "kernel launch");
+    }
+    return JT_OK;
+}
+
+void drop_graph(jt_tree t) {
+    if (t->gexec) (void)hipGraphExecDestroy(t->gexec);
+    if (t->graph) (void)hipGraphDestroy(t->graph);
+    t->gexec = nullptr;
+    t->graph = nullptr;
+}
+
+template <class T>
+const T *region(const jt_tree t, size_t off) {
+    return reinterpret_cast<const T *>(t->ws + off);
+}
+
+jt_status read_slot(jt_tree t, int32_t slot, double *log_z, bool *zero) {
+    const jt::Plan &P = t->plan;
+    int32_t flag = 0;
+    double lz = 0.0;
+    hipError_t e = hipStreamSynchronize(t->stream);
+    if (e != hipSuccess) return hip_err(e, "stream synchronize");
+    e = hipMemcpy(&flag, t->ws + P.off_flag + (size_t)slot * sizeof(int32_t), sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_err(e, "read flag");
+    e = hipMemcpy(&lz, t->ws + P.off_lam + ((size_t)slot * P.lam_stride + JT_LAM_LOGZ(P.n_cliques)) * sizeof(double),
+                  sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_err(e, "read log Z");
+    *zero = flag != 0;
+    if (log_z) *log_z = *zero ? -INFINITY : lz;
+    return JT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *jt_last_error(void) { return g_err.c_str(); }
+
+jt_status jt_compile_index_maps(const jt_tree_desc *desc, jt_tree *out, size_t *device_bytes) {
+    try {
+        if (!out || !device_bytes) return set_err(JT_E_ARG, "out or device_bytes is NULL");
+        *out = nullptr;
+        jt_tree t = new jt_tree_s();
+        std::string err;
+        const jt_status rc = jt::compile_plan(desc, t->plan, err);
+        if (rc != JT_OK) {
+            delete t;
+            return set_err(rc, err);
+        }
+        const jt::Plan &P = t->plan;
+        t->ev_vars.assign(P.n_slots, {});
+        t->ev_states.assign(P.n_slots, {});
+        t->ev_dirty.assign(P.n_slots, 1);
+        t->ev_idx_host.assign((size_t)P.n_slots * P.ev_idx_stride, 0);
+        t->ev_ent_host.assign((size_t)P.n_slots * P.ev_ent_stride, JtEv{0, 1, 1, 0});
+        *device_bytes = P.total_bytes;
+        *out = t;
+        g_err.clear();
+        return JT_OK;
+    } catch (const std::bad_alloc &) {
+        return set_err(JT_E_NO_MEM, "host allocation failed");
+    } catch (...) {
+        return set_err(JT_E_ARG, "unexpected failure in jt_compile_index_maps");
+    }
+}
+
+jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_potentials, void *hip_stream) {
+    if (jt_status rc = check_tree(t)) return rc;
+    const jt::Plan &P = t->plan;
+    if (!workspace || !init_potentials) return set_err(JT_E_ARG, "workspace or init_potentials is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return set_err(JT_E_ARG, "workspace not 256-byte aligned");
+    if (bytes < P.total_bytes)
+        return set_err(JT_E_NO_MEM, "workspace of " + std::to_string(bytes) + " bytes, need " + std::to_string(P.total_bytes));
+    drop_graph(t);
+    t->ws = static_cast<char *>(workspace);
+    t->ws_bytes = bytes;
+    t->stream = static_cast<hipStream_t>(hip_stream);
+    hipStream_t s = t->stream;
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(t->ws + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e = up(P.off_meta, P.meta.data(), P.meta.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(P.off_views, P.views.data(), P.views.size() * sizeof(JtView));
+    if (e == hipSuccess) e = up(P.off_gathers, P.gathers.data(), P.gathers.size() * sizeof(JtGather));
+    if (e == hipSuccess) e = up(P.off_items, P.items.data(), P.items.size() * sizeof(JtItem));
+    if (e == hipSuccess) e = up(P.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(JtTask));
+    if (e == hipSuccess) e = up(P.off_msgs, P.msgs.data(), P.msgs.size() * sizeof(JtMsg));
+    if (e == hipSuccess) e = up(P.off_child, P.child_edges.data(), P.child_edges.size() * sizeof(int32_t));
+    // initial tables into the aligned layout, one copy per clique
+    int64_t src_off = 0;
+    for (int32_t c = 0; c < P.n_cliques && e == hipSuccess; ++c) {
+        const jt::CliqueInfo &C = P.cl[c];
+        e = hipMemcpyAsync(t->ws + P.off_init + C.init_off * sizeof(float), init_potentials + src_off,
+                           (size_t)C.size * sizeof(float), hipMemcpyDefault, s);
+        src_off += C.size;
+    }
+    if (e != hipSuccess) return hip_err(e, "jt_bind upload");
+    JtDev &d = t->dev;
+    std::memset(&d, 0, sizeof(d));
+    d.meta = region<int32_t>(t, P.off_meta);
+    d.views = region<JtView>(t, P.off_views);
+    d.gathers = region<JtGather>(t, P.off_gathers);
+    d.items = region<JtItem>(t, P.off_items);
+    d.tasks = region<JtTask>(t, P.off_tasks);
+    d.msgs = region<JtMsg>(t, P.off_msgs);
+    d.child_edges = region<int32_t>(t, P.off_child);
+    d.init = region<float>(t, P.off_init);
+    d.coll = reinterpret_cast<float *>(t->ws + P.off_coll);
+    d.out = reinterpret_cast<float *>(t->ws + P.off_out);
+    d.sep = reinterpret_cast<float *>(t->ws + P.off_sep);
+    d.partial = reinterpret_cast<float *>(t->ws + P.off_partial);
+    d.lam = reinterpret_cast<double *>(t->ws + P.off_lam);
+    d.scale = reinterpret_cast<float *>(t->ws + P.off_scale);
+    d.flag = reinterpret_cast<int32_t *>(t->ws + P.off_flag);
+    d.ev_idx = region<int32_t>(t, P.off_ev_idx);
+    d.ev_ent = region<JtEv>(t, P.off_ev_ent);
+    d.coll_stride = P.coll_stride;
+    d.out_stride = P.out_stride;
+    d.sep_stride = P.sep_stride;
+    d.partial_stride = P.partial_stride;
+    d.lam_stride = P.lam_stride;
+    d.scale_stride = P.scale_stride;
+    d.ev_idx_stride = P.ev_idx_stride;
+    d.ev_ent_stride = P.ev_ent_stride;
+    d.n_cliques = P.n_cliques;
+    std::fill(t->ev_dirty.begin(), t->ev_dirty.end(), 1);
+    t->bound = true;
+    t->propagated = false;
+    g_err.clear();
+    return JT_OK;
+}
+
+jt_status jt_set_evidence(jt_tree t, int32_t slot, int32_t n_obs, const int32_t *vars, const int32_t *states) {
+    if (jt_status rc = check_tree(t)) return rc;
+    const jt::Plan &P = t->plan;
+    if (slot < 0 || slot >= P.n_slots) return set_err(JT_E_ARG, "slot out of range");
+    if (n_obs < 0 || (n_obs > 0 && (!vars || !states))) return set_err(JT_E_ARG, "bad evidence arrays");
+    std::vector<int32_t> seen(P.n_vars, -1);
+    for (int32_t a = 0; a < n_obs; ++a) {
+        const int32_t v = vars[a], s = states[a];
+        if (v < 0 || v >= P.n_vars) return set_err(JT_E_ARG, "evidence variable out of range");
+        if (s < 0 || s >= P.card[v]) return set_err(JT_E_ARG, "evidence state out of range");
+        if (seen[v] >= 0 && seen[v] != s) return set_err(JT_E_ARG, "conflicting evidence for one variable");
+        seen[v] = s;
+    }
+    t->ev_vars[slot].assign(vars, vars + n_obs);
+    t->ev_states[slot].assign(states, states + n_obs);
+    t->ev_dirty[slot] = 1;
+    return JT_OK;
+}
+
+jt_status jt_propagate(jt_tree t, int32_t mode) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!t->bound) return set_err(JT_E_STATE, "jt_propagate before jt_bind");
+    if (mode != JT_MODE_FUSED && mode != JT_MODE_GRAPH && mode != JT_MODE_PLAIN)
+        return set_err(JT_E_ARG, "unknown mode");
+    if (jt_status rc = upload_evidence(t)) return rc;
+    jt_status rc = JT_OK;
+    if (mode == JT_MODE_FUSED) {
+        rc = enqueue(t, t->plan.fused);
+    } else if (mode == JT_MODE_PLAIN) {
+        rc = enqueue(t, t->plan.plain);
+    } else {
+        if (!t->gexec) {
+            hipError_t e = hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_err(e, "begin capture");
+            rc = enqueue(t, t->plan.fused);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(t->stream, &g);
+            if (rc != JT_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_err(e, "end capture");
+            t->graph = g;
+            e = hipGraphInstantiate(&t->gexec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_graph(t);
+                return hip_err(e, "graph instantiate");
+            }
+        }
+        hipError_t e = hipGraphLaunch(t->gexec, t->stream);
+        if (e != hipSuccess) return hip_err(e, "graph launch");
+    }
+    if (rc == JT_OK) t->propagated = true;
+    return rc;
+}
+
+jt_status jt_marginal(jt_tree t, int32_t slot, int32_t clique, float *out, double *log_z) {
+    if (jt_status rc = check_tree(t)) return rc;
+    const jt::Plan &P = t->plan;
+    if (slot < 0 || slot >= P.n_slots) return set_err(JT_E_ARG, "slot out of range");
+    if (clique < 0 || clique >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");
+    if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+    bool zero = false;
+    if (jt_status rc = read_slot(t, slot, log_z, &zero)) return rc;
+    if (zero) return set_err(JT_E_ZERO_EVIDENCE, "evidence has probability zero");
+    if (out) {
+        const jt::CliqueInfo &C = P.cl[clique];
+        hipError_t e = hipMemcpy(out, t->ws + P.off_out + ((size_t)slot * P.out_stride + C.out_off) * sizeof(float),
+                                 (size_t)C.size * sizeof(float), hipMemcpyDefault);
+        if (e != hipSuccess) return hip_err(e, "copy marginal");
+    }
+    return JT_OK;
+}
+
+jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z) {
+    if (jt_status rc = check_tree(t)) return rc;
+    const jt::Plan &P = t->plan;
+    if (slot < 0 || slot >= P.n_slots) return set_err(JT_E_ARG, "slot out of range");
+    if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+    bool zero = false;
+    if (jt_status rc = read_slot(t, slot, log_z, &zero)) return rc;
+    if (zero) return set_err(JT_E_ZERO_EVIDENCE, "evidence has probability zero");
+    if (out) {
+        int64_t dst = 0;
+        for (int32_t c = 0; c < P.n_cliques; ++c) {
+            const jt::CliqueInfo &C = P.cl[c];
+            hipError_t e = hipMemcpyAsync(out + dst,
+                                          t->ws + P.off_out + ((size_t)slot * P.out_stride + C.out_off) * sizeof(float),
+                                          (size_t)C.size * sizeof(float), hipMemcpyDefault, t->stream);
+            if (e != hipSuccess) return hip_err(e, "copy marginals");
+            dst += C.size;
+        }
+        hipError_t e = hipStreamSynchronize(t->stream);
+        if (e != hipSuccess) return hip_err(e, "stream synchronize");
+    }
+    return JT_OK;
+}
+
+jt_status jt_get_index_map(jt_tree t, int32_t child, int32_t side, int32_t *host_out) {
+    if (jt_status rc = check_tree(t)) return rc;
+    const jt::Plan &P = t->plan;
+    if (child < 0 || child >= P.n_cliques || P.parent[child] < 0) return set_err(JT_E_ARG, "not a child clique");
+    if ((side != 0 && side != 1) || !host_out) return set_err(JT_E_ARG, "bad side or NULL output");
+    jt::expand_map(P, side == 0 ? P.edge[child].view_child : P.edge[child].view_parent, host_out);
+    return JT_OK;
+}
+
+jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_out) {
+    if (jt_status rc = check_tree(t)) return rc;
+    const jt::Plan &P = t->plan;
+    if (child < 0 || child >= P.n_cliques || P.parent[child] < 0) return set_err(JT_E_ARG, "not a child clique");
+    if ((side != 0 && side != 1) || !host_out) return set_err(JT_E_ARG, "bad side or NULL output");
+    try {
+        const int32_t c = side == 0 ? child : P.parent[child];
+        const int64_t n = P.cl[c].size, ss = P.edge[child].ssize, m = n / ss;
+        std::vector<int32_t> map(n);
+        jt::expand_map(P, side == 0 ? P.edge[child].view_child : P.edge[child].view_parent, map.data());
+        std::vector<int64_t> fill(ss, 0);
+        for (int64_t r = 0; r < n; ++r) host_out[map[r] * m + fill[map[r]]++] = (int32_t)r;
+    } catch (const std::bad_alloc &) {
+        return set_err(JT_E_NO_MEM, "host allocation failed");
+    }
+    return JT_OK;
+}
+
+jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!out) return set_err(JT_E_ARG, "out is NULL");
+    const jt::Plan &P = t->plan;
+    auto nlaunch = [](const std::vector<jt::Launch> &L) {
+        int64_t n = 0;
+        for (const jt::Launch &l : L) n += (l.is_pass == 2 || l.count > 0) ? 1 : 0;
+        return n;
+    };
+    switch (what) {
+        case JT_Q_N_SLOTS: *out = P.n_slots; break;
+        case JT_Q_TOTAL_ENTRIES: *out = P.total_entries; break;
+        case JT_Q_TABLE_SIZE:
+            if (arg < 0 || arg >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");
+            *out = P.cl[arg].size;
+            break;
+        case JT_Q_SEP_SIZE:
+            if (arg < 0 || arg >= P.n_cliques || P.parent[arg] < 0) return set_err(JT_E_ARG, "not a child clique");
+            *out = P.edge[arg].ssize;
+            break;
+        case JT_Q_ENTRIES_PER_SWEEP: *out = P.entries_per_sweep; break;
+        case JT_Q_BYTES_FUSED: *out = P.bytes_fused; break;
+        case JT_Q_BYTES_PLAIN: *out = P.bytes_plain; break;
+        case JT_Q_N_LAUNCHES_FUSED: *out = nlaunch(P.fused); break;
+        case JT_Q_N_LAUNCHES_PLAIN: *out = nlaunch(P.plain); break;
+        case JT_Q_HEIGHT: *out = P.height + 1; break;
+        case JT_Q_DEPTH: *out = P.depth + 1; break;
+        default: return set_err(JT_E_ARG, "unknown query");
+    }
+    return JT_OK;
+}
+
+jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_ms, int32_t *n_pass,
+                     int32_t *n_finalize) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!t->bound) return set_err(JT_E_STATE, "jt_profile before jt_bind");
+    if (mode != JT_MODE_FUSED && mode != JT_MODE_PLAIN) return set_err(JT_E_ARG, "profile mode must be fused or plain");
+    if (jt_status rc = upload_evidence(t)) return rc;
+    const std::vector<jt::Launch> &L = mode == JT_MODE_FUSED ? t->plan.fused : t->plan.plain;
+    const int S = t->plan.n_slots;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    jt_status rc = JT_OK;
+    hipError_t e = hipSuccess;
+    for (const jt::Launch &l : L) {
+        if (l.is_pass != 2 && l.count == 0) continue;
+        hipEvent_t a = nullptr, b = nullptr;
+        e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            rc = hip_err(e, "event create");
+            break;
+        }
+        ev.push_back(a);
+        ev.push_back(b);
+        kind.push_back(l.is_pass);
+        e = hipEventRecord(a, t->stream);
+        if (e == hipSuccess) {
+            if (l.is_pass == 2)
+                e = jt_launch_plain_init(t->dev, S, t->stream);
+            else
+                e = l.is_pass ? jt_launch_pass(t->dev, l.begin, l.count, S, t->stream)
+                              : jt_launch_finalize(t->dev, l.begin, l.count, S, t->stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(b, t->stream);
+        if (e != hipSuccess) {
+            rc = hip_err(e, "profiled launch");
+            break;
+        }
+    }
+    double tp = 0.0, tf = 0.0;
+    int np = 0, nf = 0;
+    if (rc == JT_OK) {
+        e = hipStreamSynchronize(t->stream);
+        if (e != hipSuccess) rc = hip_err(e, "stream synchronize");
+    }
+    for (size_t i = 0; rc == JT_OK && i < kind.size(); ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        if (e != hipSuccess) {
+            rc = hip_err(e, "event elapsed");
+            break;
+        }
+        if (kind[i] == 1) {
+            tp += ms;
+            ++np;
+        } else if (kind[i] == 0) {
+            tf += ms;
+            ++nf;
+        }
+    }
+    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    if (rc != JT_OK) return rc;
+    t->propagated = true;
+    if (pass_ms) *pass_ms = tp;
+    if (finalize_ms) *finalize_ms = tf;
+    if (n_pass) *n_pass = np;
+    if (n_finalize) *n_finalize = nf;
+    return JT_OK;
+}
+
+void jt_free(jt_tree t) {
+    if (!t) return;
+    drop_graph(t);
+    delete t;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// jt_internal.h -- plan structures shared by the host planner and the HIP
+// kernels of the junction-tree message engine.  Plain structs of fixed-width
+// integers so the same bytes are valid on host and device.
+//
+// Index mapping in factored form.  A clique table phi_X is cut into tiles of
+// T consecutive entries, T being the product of the innermost (fastest)
+// variables' cardinalities (an innermost variable may be split into a high
+// and a low digit when a divisor of its cardinality fits).  Entry r = o*T + i
+// then has its state string split into the tile's (outer) digits and the
+// in-tile (inner) digits, and the separator index of Sec. 3.1's mapping rule
+// is a sum of two parts:
+//     j(r) = Jin[i] + Jout[o].
+// Jin has T entries and Jout |phi_X|/T entries, so the cluster-separator
+// mapping (the single table of CSM, or the paper's |phi_S| lists) costs no
+// per-entry index storage and no per-entry division on the device.
+#pragma once
+#include <stdint.h>
+
+#define JT_WAVE 64
+#define JT_BLOCK 256
+#define JT_WAVES_PER_BLOCK (JT_BLOCK / JT_WAVE)
+#define JT_TILE_MAX 256           /* one wave covers a tile: 64 lanes x 4 entries */
+#define JT_NG_REG 8               /* gathers whose Jin values live in registers */
+#define JT_LDS_RATIO_FLOATS 8192  /* 32 KiB of LDS for staged ratio tables */
+#define JT_UNROLL 4               /* tiles in flight per wave */
+
+// One clique table seen through one separator (or through the empty
+// separator, for the table's total).
+typedef struct {
+    int64_t jin_off;        // int32 meta: Jin[T]
+    int64_t jout_off;       // int32 meta: Jout[n_tiles]
+    int64_t kout_tile_off;  // int32 meta: tile offset of each kept-outer configuration
+    int64_t kout_j_off;     // int32 meta: separator offset of each kept-outer configuration
+    int64_t rout_tile_off;  // int32 meta: tile offset of each reduced-outer configuration
+    int64_t perm_off;       // int32 meta: in-tile positions grouped by class, ascending
+    int64_t clsj_off;       // int32 meta: separator offset of each class
+    int32_t n_kout, n_rout, n_cls, m_in;
+    int32_t ssize, clique;
+} JtView;
+
+// A separator table multiplied into the entries of a pass.
+typedef struct {
+    int32_t view;     // view of the pass's clique through that separator
+    int32_t sep_off;  // float offset of the table inside the per-slot separator region
+    int32_t ssize;
+    int32_t lds_off;  // float offset of its LDS copy, -1 = read from global memory
+} JtGather;
+
+enum { JT_SRC_INIT = 0, JT_SRC_COLL = 1, JT_SRC_OUT = 2 };
+enum { JT_DST_NONE = -1, JT_DST_COLL = 1, JT_DST_OUT = 2 };
+
+// One streaming pass over one clique table (per slot):
+//   v = src[r] * [evidence] * prod_g ratio_g[j_g(r)] * scale
+//   if dst: dst[r] = v;   if out_view: partial[j_out(r)] += v
+typedef struct {
+    int32_t clique, T, vec, n_tiles;
+    int32_t src_kind, dst_kind;
+    int64_t src_off, dst_off;   // float offsets (init region, or per-slot region)
+    int32_t n_gather, gather_base;
+    int32_t n_gather_lds, lds_floats;
+    int32_t scale_clique;       // -1: no scaling
+    int32_t ev;                 // 1: enter this slot's evidence of `clique`
+    int32_t out_view;           // -1: no reduction output
+    int32_t tpg;                // tiles per group
+    int32_t nsplit;             // groups per kept-outer configuration
+    int32_t n_groups;
+    int64_t partial_off;        // float offset in the per-slot partial region
+} JtItem;
+
+// A block's share of an item: groups [g0, g1), spread over the block's waves.
+typedef struct {
+    int32_t item, g0, g1, pad;
+} JtTask;
+
+enum {
+    JT_MSG_COLLECT = 0,   // child -> parent, collect sweep
+    JT_MSG_TOTAL = 1,     // root table total: log Z and the root's output scale
+    JT_MSG_DIST = 2,      // parent -> child, distribute sweep
+    JT_MSG_PLAIN = 3,     // one message of the one-at-a-time schedule
+    JT_MSG_PLAIN_TOTAL = 4 // total of a calibrated table, one-at-a-time schedule
+};
+
+// Finalization of one message: sum the split partials into the new
+// separator table, rescale it to mean one, form the ratio, update log-scales.
+typedef struct {
+    int32_t kind;
+    int32_t edge;           // separator id (= child clique), -1 for a total
+    int32_t from, to;
+    int32_t ssize, nsplit;
+    int64_t partial_off;
+    int32_t child_base, n_children;  // children edges of `from` (collect log-scale sum)
+    int32_t sepc_off, sepd_off;      // separator tables in the per-slot region
+} JtMsg;
+
+// One digit condition of hard evidence: entry kept iff
+// (index / stride) % card == digit, index being the tile index for outer
+// digits and the in-tile position for inner ones.
+typedef struct {
+    int32_t outer, stride, card, digit;
+} JtEv;
+
+// Per-slot log-scale layout (doubles): [0,nc) collect separators, [nc,2nc)
+// distribute separators, [2nc,3nc) clique collect scales, [3nc] log Z.
+#define JT_LAM_SC(nc) 0
+#define JT_LAM_SD(nc) (nc)
+#define JT_LAM_COLL(nc) (2 * (nc))
+#define JT_LAM_LOGZ(nc) (3 * (nc))
+
+// Everything a kernel needs, passed by value.
+typedef struct {
+    const int32_t *meta;
+    const JtView *views;
+    const JtGather *gathers;
+    const JtItem *items;
+    const JtTask *tasks;
+    const JtMsg *msgs;
+    const int32_t *child_edges;
+    const float *init;
+    float *coll;
+    float *out;
+    float *sep;
+    float *partial;
+    double *lam;
+    float *scale;
+    int32_t *flag;
+    const int32_t *ev_idx;
+    const JtEv *ev_ent;
+    int64_t coll_stride, out_stride, sep_stride, partial_stride;
+    int64_t lam_stride, scale_stride, ev_idx_stride, ev_ent_stride;
+    int32_t n_cliques, pad;
+} JtDev;

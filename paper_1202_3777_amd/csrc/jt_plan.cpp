@@ -1,0 +1,781 @@
+// jt_plan.cpp -- compile a junction tree into the engine's device plan.
+//
+// Host only.  Validates the tree (Sec. 2.1: cliques, separators
+// S_ij = X_i intersect X_j, one designated root), derives every
+// cluster-separator index mapping of Sec. 3.1-3.2 once (the paper
+// precomputes them when the tree is established) in factored tile form, and
+// lays out the level schedule of the collect / distribute sweeps
+// (Algorithms 2-4) plus the one-message-at-a-time schedule.
+#include "jt_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <limits>
+
+namespace jt {
+
+namespace {
+
+constexpr int64_t kAlignFloats = 64;       // 256-byte alignment of every table
+constexpr int64_t kGroupEntries = 2048;    // target entries per wave group
+constexpr int64_t kPartialMax = 65536;     // cap on split partial floats per message
+constexpr int64_t kMaxMeta = int64_t(1) << 30;
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+jt_status fail(std::string &err, jt_status code, const std::string &msg) {
+    err = msg;
+    return code;
+}
+
+bool has_var(const std::vector<int32_t> &sorted_vars, int32_t v) {
+    return std::binary_search(sorted_vars.begin(), sorted_vars.end(), v);
+}
+
+// Choose the tile of a clique: the largest product of the innermost
+// cardinalities that fits JT_TILE_MAX, splitting the next variable into a
+// high and a low digit when a divisor of its cardinality still fits.
+void shape_clique(const std::vector<int32_t> &card, CliqueInfo &C) {
+    const int m = (int)C.vars.size();
+    std::vector<int64_t> st(m);
+    int64_t s = 1;
+    for (int i = m - 1; i >= 0; --i) {
+        st[i] = s;
+        s *= card[C.vars[i]];
+    }
+    C.size = s;
+    int64_t prod = 1;
+    int i = m - 1;
+    while (i >= 0 && prod * card[C.vars[i]] <= JT_TILE_MAX) {
+        prod *= card[C.vars[i]];
+        --i;
+    }
+    int split = -1;
+    int64_t f = 1;
+    if (i >= 0) {
+        int64_t k = card[C.vars[i]];
+        for (int64_t d = k - 1; d >= 2; --d)
+            if (k % d == 0 && prod * d <= JT_TILE_MAX) {
+                f = d;
+                break;
+            }
+        if (f > 1) split = i;
+    }
+    C.T = (int32_t)(prod * f);
+    C.n_tiles = C.size / C.T;
+    C.vec = (C.T % 4 == 0) ? 4 : 1;
+    C.digits.clear();
+    for (int a = 0; a < m; ++a) {
+        const int32_t v = C.vars[a];
+        const int32_t k = card[v];
+        if (a == split) {
+            VDigit hi{v, (int32_t)(k / f), st[a] * f, f, true, (st[a] * f) / C.T};
+            VDigit lo{v, (int32_t)f, st[a], 1, false, 0};
+            C.digits.push_back(hi);
+            C.digits.push_back(lo);
+        } else {
+            const bool outer = (a <= i);
+            VDigit d{v, k, st[a], 1, outer, outer ? st[a] / C.T : 0};
+            C.digits.push_back(d);
+        }
+    }
+}
+
+// Build the factored mapping tables of clique c through edge e (or through
+// the empty separator when e < 0) and return the view index.
+int32_t build_view(Plan &P, int32_t c, int32_t e) {
+    const CliqueInfo &C = P.cl[c];
+    JtView V;
+    std::memset(&V, 0, sizeof(V));
+    V.clique = c;
+    V.ssize = (int32_t)(e >= 0 ? P.edge[e].ssize : 1);
+    const size_t nd = C.digits.size();
+    std::vector<int64_t> ws(nd, 0);
+    if (e >= 0) {
+        const EdgeInfo &E = P.edge[e];
+        for (size_t k = 0; k < nd; ++k)
+            for (size_t p = 0; p < E.vars.size(); ++p)
+                if (E.vars[p] == C.digits[k].var) ws[k] = E.sst[p] * C.digits[k].w;
+    }
+    std::vector<int32_t> &M = P.meta;
+    // Jin: separator contribution of the in-tile digits
+    V.jin_off = (int64_t)M.size();
+    for (int64_t i = 0; i < C.T; ++i) {
+        int64_t j = 0;
+        for (size_t k = 0; k < nd; ++k)
+            if (!C.digits[k].outer) j += ((i / C.digits[k].stride) % C.digits[k].card) * ws[k];
+        M.push_back((int32_t)j);
+    }
+    // Jout: separator contribution of the tile digits
+    V.jout_off = (int64_t)M.size();
+    for (int64_t o = 0; o < C.n_tiles; ++o) {
+        int64_t j = 0;
+        for (size_t k = 0; k < nd; ++k)
+            if (C.digits[k].outer) j += ((o / C.digits[k].ostride) % C.digits[k].card) * ws[k];
+        M.push_back((int32_t)j);
+    }
+    // kept / reduced outer digits and kept inner digits, listed order
+    std::vector<size_t> ko, ro, ki;
+    for (size_t k = 0; k < nd; ++k) {
+        if (C.digits[k].outer)
+            (ws[k] ? ko : ro).push_back(k);
+        else if (ws[k])
+            ki.push_back(k);
+    }
+    auto count = [&](const std::vector<size_t> &ds) {
+        int64_t n = 1;
+        for (size_t k : ds) n *= C.digits[k].card;
+        return n;
+    };
+    const int64_t n_kout = count(ko), n_rout = count(ro), n_cls = count(ki);
+    V.n_kout = (int32_t)n_kout;
+    V.n_rout = (int32_t)n_rout;
+    V.n_cls = (int32_t)n_cls;
+    V.m_in = (int32_t)(C.T / n_cls);
+    // decode a mixed-radix index over a digit list (last listed fastest)
+    auto decode = [&](int64_t x, const std::vector<size_t> &ds, int64_t &tile, int64_t &j) {
+        tile = 0;
+        j = 0;
+        for (size_t a = ds.size(); a-- > 0;) {
+            const VDigit &d = C.digits[ds[a]];
+            const int64_t dig = x % d.card;
+            x /= d.card;
+            tile += dig * d.ostride;
+            j += dig * ws[ds[a]];
+        }
+    };
+    V.kout_tile_off = (int64_t)M.size();
+    for (int64_t k = 0; k < n_kout; ++k) {
+        int64_t t, j;
+        decode(k, ko, t, j);
+        M.push_back((int32_t)t);
+    }
+    V.kout_j_off = (int64_t)M.size();
+    for (int64_t k = 0; k < n_kout; ++k) {
+        int64_t t, j;
+        decode(k, ko, t, j);
+        M.push_back((int32_t)j);
+    }
+    V.rout_tile_off = (int64_t)M.size();
+    for (int64_t q = 0; q < n_rout; ++q) {
+        int64_t t, j;
+        decode(q, ro, t, j);
+        M.push_back((int32_t)t);
+    }
+    // in-tile positions grouped by class (kept inner digits), ascending
+    V.perm_off = (int64_t)M.size();
+    M.resize(M.size() + C.T);
+    std::vector<int64_t> fill(n_cls, 0);
+    for (int64_t i = 0; i < C.T; ++i) {
+        int64_t cls = 0;
+        for (size_t k : ki) cls = cls * C.digits[k].card + (i / C.digits[k].stride) % C.digits[k].card;
+        M[V.perm_off + cls * V.m_in + fill[cls]++] = (int32_t)i;
+    }
+    V.clsj_off = (int64_t)M.size();
+    for (int64_t cls = 0; cls < n_cls; ++cls) M.push_back(M[V.jin_off + M[V.perm_off + cls * V.m_in]]);
+    P.views.push_back(V);
+    return (int32_t)P.views.size() - 1;
+}
+
+struct GatherSpec {
+    int32_t edge;
+    bool dist;   // ratio of the distribute sweep (else the collect table)
+};
+
+// Append one pass item and the tasks that cover it.
+int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t dst_kind,
+                 int64_t dst_off, const std::vector<GatherSpec> &gs, int32_t scale_clique,
+                 int32_t out_view, int64_t partial_off, int64_t &bytes_acc) {
+    const CliqueInfo &C = P.cl[c];
+    JtItem it;
+    std::memset(&it, 0, sizeof(it));
+    it.clique = c;
+    it.T = C.T;
+    it.vec = C.vec;
+    it.n_tiles = (int32_t)C.n_tiles;
+    it.src_kind = src_kind;
+    it.src_off = src_off;
+    it.dst_kind = dst_kind;
+    it.dst_off = dst_off;
+    it.gather_base = (int32_t)P.gathers.size();
+    it.n_gather = (int32_t)gs.size();
+    int32_t lds = 0, n_lds = 0;
+    bool lds_open = true;
+    for (const GatherSpec &g : gs) {
+        const EdgeInfo &E = P.edge[g.edge];
+        JtGather G;
+        G.view = (c == g.edge) ? E.view_child : E.view_parent;
+        G.sep_off = g.dist ? E.sepd_off : E.sepc_off;
+        G.ssize = (int32_t)E.ssize;
+        if (lds_open && lds + E.ssize <= JT_LDS_RATIO_FLOATS) {
+            G.lds_off = lds;
+            lds += (int32_t)E.ssize;
+            ++n_lds;
+        } else {
+            lds_open = false;
+            G.lds_off = -1;
+        }
+        P.gathers.push_back(G);
+    }
+    it.n_gather_lds = n_lds;
+    it.lds_floats = lds;
+    it.scale_clique = scale_clique;
+    it.ev = (src_kind == JT_SRC_INIT) ? 1 : 0;
+    it.out_view = out_view;
+    it.partial_off = partial_off;
+    const int64_t tiles_per_group = std::max<int64_t>(1, kGroupEntries / C.T);
+    if (out_view >= 0) {
+        const JtView &V = P.views[out_view];
+        int64_t tpg = std::min<int64_t>(V.n_rout, tiles_per_group);
+        int64_t nsplit = (V.n_rout + tpg - 1) / tpg;
+        while (nsplit * V.ssize > kPartialMax && tpg < V.n_rout) {
+            tpg *= 2;
+            nsplit = (V.n_rout + tpg - 1) / tpg;
+        }
+        it.tpg = (int32_t)tpg;
+        it.nsplit = (int32_t)nsplit;
+        it.n_groups = (int32_t)(V.n_kout * nsplit);
+    } else {
+        const int64_t tpg = std::min<int64_t>(C.n_tiles, tiles_per_group);
+        it.tpg = (int32_t)tpg;
+        it.nsplit = 1;
+        it.n_groups = (int32_t)((C.n_tiles + tpg - 1) / tpg);
+    }
+    P.items.push_back(it);
+    const int32_t idx = (int32_t)P.items.size() - 1;
+    // one group per wave, JT_WAVES_PER_BLOCK groups per block
+    for (int32_t g0 = 0; g0 < it.n_groups; g0 += JT_WAVES_PER_BLOCK) {
+        JtTask t;
+        t.item = idx;
+        t.g0 = g0;
+        t.g1 = std::min<int32_t>(it.n_groups, g0 + JT_WAVES_PER_BLOCK);
+        t.pad = 0;
+        P.tasks.push_back(t);
+    }
+    // FP32 table bytes: shared initial tables are read once for all slots
+    const int64_t tb = 4 * C.size;
+    bytes_acc += (src_kind == JT_SRC_INIT) ? tb : tb * P.n_slots;
+    if (dst_kind != JT_DST_NONE) bytes_acc += tb * P.n_slots;
+    return idx;
+}
+
+int32_t item_nsplit(const Plan &P, int32_t item) { return P.items[item].nsplit; }
+
+
+// Check, on the host, that every index the kernels derive from the plan
+// stays inside its buffer.  Run once per compiled tree; a failure here is a
+// planner bug and is reported instead of launching anything.
+bool verify_plan(const Plan &P, std::string &why) {
+    auto bad = [&](const std::string &m) {
+        why = "plan check failed: " + m;
+        return false;
+    };
+    const int64_t nm = (int64_t)P.meta.size();
+    auto in_meta = [&](int64_t off, int64_t n) { return off >= 0 && n >= 0 && off + n <= nm; };
+    auto mmax = [&](int64_t off, int64_t n) {
+        int64_t m = 0;
+        for (int64_t i = 0; i < n; ++i) m = std::max<int64_t>(m, P.meta[off + i]);
+        return m;
+    };
+    auto mmin = [&](int64_t off, int64_t n) {
+        int64_t m = 0;
+        for (int64_t i = 0; i < n; ++i) m = std::min<int64_t>(m, P.meta[off + i]);
+        return m;
+    };
+    for (size_t vi = 0; vi < P.views.size(); ++vi) {
+        const JtView &V = P.views[vi];
+        if (V.clique < 0 || V.clique >= P.n_cliques) return bad("view clique");
+        const CliqueInfo &C = P.cl[V.clique];
+        if (C.T < 1 || C.T > JT_TILE_MAX || C.T * C.n_tiles != C.size) return bad("tile shape");
+        if ((int64_t)V.n_kout * V.n_rout != C.n_tiles || (int64_t)V.n_cls * V.m_in != C.T) return bad("view counts");
+        if (!in_meta(V.jin_off, C.T) || !in_meta(V.jout_off, C.n_tiles) || !in_meta(V.kout_tile_off, V.n_kout) ||
+            !in_meta(V.kout_j_off, V.n_kout) || !in_meta(V.rout_tile_off, V.n_rout) || !in_meta(V.perm_off, C.T) ||
+            !in_meta(V.clsj_off, V.n_cls))
+            return bad("view tables outside metadata");
+        if (mmin(V.jin_off, C.T) < 0 || mmin(V.jout_off, C.n_tiles) < 0 || mmin(V.kout_j_off, V.n_kout) < 0 ||
+            mmin(V.clsj_off, V.n_cls) < 0 || mmin(V.kout_tile_off, V.n_kout) < 0 || mmin(V.rout_tile_off, V.n_rout) < 0 ||
+            mmin(V.perm_off, C.T) < 0)
+            return bad("negative index in view");
+        if (mmax(V.jin_off, C.T) + mmax(V.jout_off, C.n_tiles) >= V.ssize) return bad("separator index range");
+        if (mmax(V.kout_j_off, V.n_kout) + mmax(V.clsj_off, V.n_cls) >= V.ssize) return bad("class index range");
+        if (mmax(V.kout_tile_off, V.n_kout) + mmax(V.rout_tile_off, V.n_rout) >= C.n_tiles) return bad("tile range");
+        if (mmax(V.perm_off, C.T) >= C.T) return bad("perm range");
+    }
+    for (size_t ii = 0; ii < P.items.size(); ++ii) {
+        const JtItem &it = P.items[ii];
+        if (it.clique < 0 || it.clique >= P.n_cliques) return bad("item clique");
+        const CliqueInfo &C = P.cl[it.clique];
+        if (it.T != C.T || it.n_tiles != C.n_tiles || (it.vec != 1 && it.vec != 4) || (it.vec == 4 && it.T % 4))
+            return bad("item shape");
+        const int64_t src_lim = it.src_kind == JT_SRC_INIT ? P.init_floats
+                                : it.src_kind == JT_SRC_COLL ? P.coll_stride : P.out_stride;
+        if (it.src_off < 0 || it.src_off + C.size > src_lim || it.src_off % 4) return bad("item source range");
+        if (it.dst_kind != JT_DST_NONE) {
+            const int64_t dst_lim = it.dst_kind == JT_DST_COLL ? P.coll_stride : P.out_stride;
+            if (it.dst_off < 0 || it.dst_off + C.size > dst_lim || it.dst_off % 4) return bad("item destination range");
+        }
+        if (it.gather_base < 0 || it.gather_base + it.n_gather > (int32_t)P.gathers.size()) return bad("gather range");
+        if (it.n_gather_lds > it.n_gather || it.lds_floats > JT_LDS_RATIO_FLOATS) return bad("LDS budget");
+        for (int g = 0; g < it.n_gather; ++g) {
+            const JtGather &G = P.gathers[it.gather_base + g];
+            if (G.view < 0 || G.view >= (int32_t)P.views.size() || P.views[G.view].clique != it.clique) return bad("gather view");
+            if (P.views[G.view].ssize != G.ssize) return bad("gather size");
+            if (G.sep_off < 0 || G.sep_off + (int64_t)G.ssize > P.sep_stride) return bad("gather separator range");
+            if ((g < it.n_gather_lds) != (G.lds_off >= 0)) return bad("gather LDS order");
+            if (G.lds_off >= 0 && G.lds_off + G.ssize > it.lds_floats) return bad("gather LDS range");
+        }
+        if (it.scale_clique >= P.n_cliques) return bad("scale clique");
+        if (it.tpg < 1 || it.nsplit < 1 || it.n_groups < 1) return bad("grouping");
+        if (it.out_view >= 0) {
+            if (it.out_view >= (int32_t)P.views.size()) return bad("output view");
+            const JtView &V = P.views[it.out_view];
+            if (V.clique != it.clique) return bad("output view clique");
+            if ((int64_t)it.tpg * it.nsplit < V.n_rout || (int64_t)it.tpg * (it.nsplit - 1) >= V.n_rout)
+                return bad("split cover");
+            if ((int64_t)it.n_groups != (int64_t)V.n_kout * it.nsplit) return bad("group count");
+            if (it.partial_off < 0 || it.partial_off + (int64_t)it.nsplit * V.ssize > P.partial_stride)
+                return bad("partial range");
+        } else {
+            if ((int64_t)it.tpg * it.n_groups < C.n_tiles || (int64_t)it.tpg * (it.n_groups - 1) >= C.n_tiles)
+                return bad("tile cover");
+        }
+    }
+    for (const JtTask &t : P.tasks) {
+        if (t.item < 0 || t.item >= (int32_t)P.items.size()) return bad("task item");
+        if (t.g0 < 0 || t.g1 > P.items[t.item].n_groups || t.g0 >= t.g1) return bad("task groups");
+    }
+    for (const JtMsg &m : P.msgs) {
+        if (m.ssize < 1 || m.nsplit < 1) return bad("message shape");
+        if (m.partial_off < 0 || m.partial_off + (int64_t)m.nsplit * m.ssize > P.partial_stride) return bad("message partial");
+        if (m.from < 0 || m.from >= P.n_cliques) return bad("message source");
+        if (m.kind == JT_MSG_COLLECT || m.kind == JT_MSG_DIST || m.kind == JT_MSG_PLAIN) {
+            if (m.edge < 0 || m.edge >= P.n_cliques || P.parent[m.edge] < 0) return bad("message edge");
+            if (m.ssize != P.edge[m.edge].ssize) return bad("message separator size");
+            if (m.sepc_off + (int64_t)m.ssize > P.sep_stride || m.sepd_off + (int64_t)m.ssize > P.sep_stride)
+                return bad("message separator range");
+            if (m.to < 0 || m.to >= P.n_cliques) return bad("message target");
+        }
+        if (m.child_base < 0 || m.child_base + m.n_children > (int32_t)P.child_edges.size()) return bad("children range");
+    }
+    for (const std::vector<Launch> *L : {&P.fused, &P.plain})
+        for (const Launch &l : *L) {
+            if (l.is_pass == 1 && (l.begin < 0 || l.begin + l.count > (int32_t)P.tasks.size())) return bad("launch tasks");
+            if (l.is_pass == 0 && (l.begin < 0 || l.begin + l.count > (int32_t)P.msgs.size())) return bad("launch msgs");
+        }
+    for (int32_t c = 0; c < P.n_cliques; ++c)
+        for (const VDigit &d : P.cl[c].digits)
+            if (d.card < 1 || (d.outer ? d.ostride : d.stride) < 1) return bad("digit shape");
+    return true;
+}
+
+}  // namespace
+
+jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
+    if (!desc) return fail(err, JT_E_ARG, "desc is NULL");
+    const int32_t nv = desc->n_vars, nc = desc->n_cliques;
+    if (nv < 0) return fail(err, JT_E_ARG, "n_vars < 0");
+    if (nc < 1) return fail(err, JT_E_ARG, "n_cliques < 1");
+    if (desc->n_slots < 1 || desc->n_slots > (1 << 20)) return fail(err, JT_E_ARG, "n_slots out of range");
+    if ((nv > 0 && !desc->card) || !desc->clique_off || !desc->clique_vars || !desc->parent)
+        return fail(err, JT_E_ARG, "NULL array in desc");
+    P = Plan();
+    P.n_vars = nv;
+    P.n_cliques = nc;
+    P.n_slots = desc->n_slots;
+    P.card.assign(desc->card, desc->card + nv);
+    P.parent.assign(desc->parent, desc->parent + nc);
+    for (int32_t v = 0; v < nv; ++v)
+        if (P.card[v] < 1) return fail(err, JT_E_ARG, "card[" + std::to_string(v) + "] < 1");
+    if (desc->clique_off[0] != 0) return fail(err, JT_E_ARG, "clique_off[0] != 0");
+    P.cl.resize(nc);
+    std::vector<std::vector<int32_t>> sorted_vars(nc);
+    std::vector<int32_t> stamp(nv, -1);
+    for (int32_t c = 0; c < nc; ++c) {
+        const int64_t a = desc->clique_off[c], b = desc->clique_off[c + 1];
+        if (b < a || b - a > 64) return fail(err, JT_E_ARG, "clique " + std::to_string(c) + ": bad variable count");
+        int64_t size = 1;
+        for (int64_t k = a; k < b; ++k) {
+            const int32_t v = desc->clique_vars[k];
+            if (v < 0 || v >= nv) return fail(err, JT_E_ARG, "clique " + std::to_string(c) + ": variable out of range");
+            if (stamp[v] == c) return fail(err, JT_E_ARG, "clique " + std::to_string(c) + ": repeated variable");
+            stamp[v] = c;
+            size *= P.card[v];
+            if (size > std::numeric_limits<int32_t>::max())
+                return fail(err, JT_E_TOO_LARGE, "clique " + std::to_string(c) + ": table has 2^31 or more entries");
+            P.cl[c].vars.push_back(v);
+        }
+        sorted_vars[c] = P.cl[c].vars;
+        std::sort(sorted_vars[c].begin(), sorted_vars[c].end());
+    }
+    // one root, parents in range, every clique reachable from the root
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t p = P.parent[c];
+        if (p == -1) {
+            if (P.root >= 0) return fail(err, JT_E_NOT_JUNCTION_TREE, "more than one root");
+            P.root = c;
+        } else if (p < 0 || p >= nc || p == c) {
+            return fail(err, JT_E_NOT_JUNCTION_TREE, "parent of clique " + std::to_string(c) + " out of range");
+        }
+    }
+    if (P.root < 0) return fail(err, JT_E_NOT_JUNCTION_TREE, "no root (parent == -1)");
+    for (int32_t c = 0; c < nc; ++c)
+        if (P.parent[c] >= 0) P.cl[P.parent[c]].children.push_back(c);
+    std::vector<int32_t> bfs;
+    bfs.reserve(nc);
+    bfs.push_back(P.root);
+    for (size_t h = 0; h < bfs.size(); ++h)
+        for (int32_t ch : P.cl[bfs[h]].children) {
+            P.cl[ch].depth = P.cl[bfs[h]].depth + 1;
+            bfs.push_back(ch);
+        }
+    if ((int32_t)bfs.size() != nc) return fail(err, JT_E_NOT_JUNCTION_TREE, "parent links contain a cycle");
+    // running intersection: the cliques holding a variable are connected
+    {
+        std::vector<std::vector<int32_t>> holders(nv);
+        for (int32_t c = 0; c < nc; ++c)
+            for (int32_t v : P.cl[c].vars) holders[v].push_back(c);
+        std::vector<int32_t> seen(nc, -1), queue;
+        for (int32_t v = 0; v < nv; ++v) {
+            if (holders[v].empty()) continue;
+            queue.assign(1, holders[v][0]);
+            seen[holders[v][0]] = v;
+            for (size_t h = 0; h < queue.size(); ++h) {
+                const int32_t x = queue[h];
+                auto visit = [&](int32_t y) {
+                    if (y >= 0 && seen[y] != v && has_var(sorted_vars[y], v)) {
+                        seen[y] = v;
+                        queue.push_back(y);
+                    }
+                };
+                visit(P.parent[x]);
+                for (int32_t ch : P.cl[x].children) visit(ch);
+            }
+            if (queue.size() != holders[v].size())
+                return fail(err, JT_E_NOT_JUNCTION_TREE,
+                            "running intersection violated for variable " + std::to_string(v));
+        }
+    }
+    for (size_t h = bfs.size(); h-- > 0;) {
+        const int32_t c = bfs[h];
+        if (P.parent[c] >= 0)
+            P.cl[P.parent[c]].height = std::max(P.cl[P.parent[c]].height, P.cl[c].height + 1);
+    }
+    P.height = P.cl[P.root].height;
+    for (int32_t c = 0; c < nc; ++c) P.depth = std::max(P.depth, P.cl[c].depth);
+    P.home.assign(nv, -1);
+    for (int32_t c = nc - 1; c >= 0; --c)
+        for (int32_t v : P.cl[c].vars) P.home[v] = c;
+
+    // tiles, table regions
+    for (int32_t c = 0; c < nc; ++c) {
+        shape_clique(P.card, P.cl[c]);
+        P.total_entries += P.cl[c].size;
+        if (P.cl[c].n_tiles > (int64_t(1) << 26))
+            return fail(err, JT_E_TOO_LARGE, "clique " + std::to_string(c) + ": too many tiles");
+    }
+    for (int32_t c = 0; c < nc; ++c) {
+        CliqueInfo &C = P.cl[c];
+        C.init_off = P.init_floats;
+        P.init_floats += align_up(C.size, kAlignFloats);
+        C.out_off = P.out_stride;
+        P.out_stride += align_up(C.size, kAlignFloats);
+        if (!C.children.empty()) {
+            C.coll_off = P.coll_stride;
+            P.coll_stride += align_up(C.size, kAlignFloats);
+        }
+    }
+    // separators: ascending variable id, row-major, last fastest
+    P.edge.resize(nc);
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t p = P.parent[c];
+        if (p < 0) continue;
+        EdgeInfo &E = P.edge[c];
+        std::set_intersection(sorted_vars[c].begin(), sorted_vars[c].end(), sorted_vars[p].begin(),
+                              sorted_vars[p].end(), std::back_inserter(E.vars));
+        E.sst.assign(E.vars.size(), 1);
+        int64_t s = 1;
+        for (size_t k = E.vars.size(); k-- > 0;) {
+            E.sst[k] = s;
+            s *= P.card[E.vars[k]];
+        }
+        E.ssize = s;
+        E.sepc_off = (int32_t)P.sep_stride;
+        P.sep_stride += align_up(s, kAlignFloats);
+        E.sepd_off = (int32_t)P.sep_stride;
+        P.sep_stride += align_up(s, kAlignFloats);
+        if (P.sep_stride > std::numeric_limits<int32_t>::max())
+            return fail(err, JT_E_TOO_LARGE, "separator tables exceed 2^31 floats");
+        P.entries_per_sweep += P.cl[c].size + P.cl[p].size;
+    }
+    // views: every clique through each incident separator and through nothing
+    for (int32_t c = 0; c < nc; ++c) {
+        if (P.parent[c] >= 0) {
+            P.edge[c].view_child = build_view(P, c, c);
+            P.edge[c].view_parent = build_view(P, P.parent[c], c);
+            P.cl[c].parent_view = P.edge[c].view_child;
+        }
+        P.cl[c].total_view = build_view(P, c, -1);
+        if ((int64_t)P.meta.size() > kMaxMeta) return fail(err, JT_E_TOO_LARGE, "index metadata too large");
+    }
+    // ---------------- fused level schedule ----------------
+    auto add_partial = [&](int64_t floats) {
+        const int64_t off = P.partial_stride;
+        P.partial_stride += align_up(floats, kAlignFloats);
+        return off;
+    };
+    std::vector<std::vector<int32_t>> by_height(P.height + 1), by_depth(P.depth + 1);
+    for (int32_t c = 0; c < nc; ++c) {
+        by_height[P.cl[c].height].push_back(c);
+        by_depth[P.cl[c].depth].push_back(c);
+    }
+    int64_t bytes = 0;
+    for (int32_t h = 0; h <= P.height; ++h) {
+        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size();
+        std::vector<JtMsg> level_msgs;
+        for (int32_t c : by_height[h]) {
+            const CliqueInfo &C = P.cl[c];
+            std::vector<GatherSpec> gs;
+            for (int32_t ch : C.children) gs.push_back({ch, false});
+            const bool is_root = (c == P.root);
+            const int32_t view = is_root ? C.total_view : C.parent_view;
+            // partial size is known once the item's split is chosen: add the
+            // item first with a placeholder, then patch its offset.
+            const int32_t it = add_item(P, c, JT_SRC_INIT, C.init_off, C.children.empty() ? JT_DST_NONE : JT_DST_COLL,
+                                        C.coll_off, gs, -1, view, 0, bytes);
+            const int64_t ss = P.views[view].ssize;
+            const int64_t poff = add_partial(ss * item_nsplit(P, it));
+            P.items[it].partial_off = poff;
+            JtMsg m;
+            std::memset(&m, 0, sizeof(m));
+            m.kind = is_root ? JT_MSG_TOTAL : JT_MSG_COLLECT;
+            m.edge = is_root ? -1 : c;
+            m.from = c;
+            m.to = is_root ? -1 : P.parent[c];
+            m.ssize = (int32_t)ss;
+            m.nsplit = P.items[it].nsplit;
+            m.partial_off = poff;
+            m.child_base = (int32_t)P.child_edges.size();
+            m.n_children = (int32_t)C.children.size();
+            for (int32_t ch : C.children) P.child_edges.push_back(ch);
+            m.sepc_off = is_root ? 0 : P.edge[c].sepc_off;
+            m.sepd_off = is_root ? 0 : P.edge[c].sepd_off;
+            level_msgs.push_back(m);
+        }
+        for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
+        P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        P.fused.push_back({0, m0, (int32_t)P.msgs.size() - m0});
+    }
+    for (int32_t d = 0; d <= P.depth; ++d) {
+        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size();
+        std::vector<JtMsg> level_msgs;
+        for (int32_t c : by_depth[d]) {
+            const CliqueInfo &C = P.cl[c];
+            std::vector<GatherSpec> gs;
+            if (c != P.root) gs.push_back({c, true});
+            const bool leaf = C.children.empty();
+            const int32_t src_kind = leaf ? JT_SRC_INIT : JT_SRC_COLL;
+            const int64_t src_off = leaf ? C.init_off : C.coll_off;
+            if (leaf) {
+                add_item(P, c, src_kind, src_off, JT_DST_OUT, C.out_off, gs, c, -1, 0, bytes);
+                continue;
+            }
+            for (size_t k = 0; k < C.children.size(); ++k) {
+                const int32_t ch = C.children[k];
+                const int32_t view = P.edge[ch].view_parent;
+                const int32_t it = add_item(P, c, src_kind, src_off, k == 0 ? JT_DST_OUT : JT_DST_NONE,
+                                            C.out_off, gs, c, view, 0, bytes);
+                const int64_t ss = P.views[view].ssize;
+                const int64_t poff = add_partial(ss * item_nsplit(P, it));
+                P.items[it].partial_off = poff;
+                JtMsg m;
+                std::memset(&m, 0, sizeof(m));
+                m.kind = JT_MSG_DIST;
+                m.edge = ch;
+                m.from = c;
+                m.to = ch;
+                m.ssize = (int32_t)ss;
+                m.nsplit = P.items[it].nsplit;
+                m.partial_off = poff;
+                m.sepc_off = P.edge[ch].sepc_off;
+                m.sepd_off = P.edge[ch].sepd_off;
+                level_msgs.push_back(m);
+            }
+        }
+        for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
+        P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        if (!level_msgs.empty()) P.fused.push_back({0, m0, (int32_t)P.msgs.size() - m0});
+    }
+    P.bytes_fused = bytes;
+
+    // ---------------- one-message-at-a-time schedule ----------------
+    // Tables live in the output region and are updated in place.
+    bytes = 0;
+    {
+        const int32_t t0 = (int32_t)P.tasks.size();
+        for (int32_t c = 0; c < nc; ++c)
+            add_item(P, c, JT_SRC_INIT, P.cl[c].init_off, JT_DST_OUT, P.cl[c].out_off, {}, -1, -1, 0, bytes);
+        P.plain_reset_task_begin = t0;
+        P.plain_reset_task_count = (int32_t)P.tasks.size() - t0;
+        P.plain.push_back({2, 0, 0});   // separators := 1, log-scales := 0
+        P.plain.push_back({1, t0, P.plain_reset_task_count});
+    }
+    auto plain_message = [&](int32_t e, int32_t from, int32_t to) {
+        const int32_t view_from = (from == e) ? P.edge[e].view_child : P.edge[e].view_parent;
+        const int32_t t0 = (int32_t)P.tasks.size();
+        const int32_t it = add_item(P, from, JT_SRC_OUT, P.cl[from].out_off, JT_DST_NONE, 0, {}, -1,
+                                    view_from, 0, bytes);
+        const int64_t ss = P.edge[e].ssize;
+        const int64_t poff = add_partial(ss * item_nsplit(P, it));
+        P.items[it].partial_off = poff;
+        P.plain.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        JtMsg m;
+        std::memset(&m, 0, sizeof(m));
+        m.kind = JT_MSG_PLAIN;
+        m.edge = e;
+        m.from = from;
+        m.to = to;
+        m.ssize = (int32_t)ss;
+        m.nsplit = P.items[it].nsplit;
+        m.partial_off = poff;
+        m.sepc_off = P.edge[e].sepc_off;
+        m.sepd_off = P.edge[e].sepd_off;
+        P.msgs.push_back(m);
+        P.plain.push_back({0, (int32_t)P.msgs.size() - 1, 1});
+        const int32_t t1 = (int32_t)P.tasks.size();
+        add_item(P, to, JT_SRC_OUT, P.cl[to].out_off, JT_DST_OUT, P.cl[to].out_off, {{e, true}}, -1, -1, 0,
+                 bytes);
+        P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
+    };
+    // Algorithm 2 (post-order) and Algorithm 3 (pre-order), children ascending
+    {
+        std::vector<std::pair<int32_t, size_t>> stack{{P.root, 0}};
+        while (!stack.empty()) {
+            auto &top = stack.back();
+            const CliqueInfo &C = P.cl[top.first];
+            if (top.second < C.children.size()) {
+                const int32_t ch = C.children[top.second++];
+                stack.push_back({ch, 0});
+            } else {
+                const int32_t c = top.first;
+                stack.pop_back();
+                if (P.parent[c] >= 0) plain_message(c, c, P.parent[c]);
+            }
+        }
+        std::vector<std::pair<int32_t, size_t>> st2{{P.root, 0}};
+        while (!st2.empty()) {
+            auto &top = st2.back();
+            const CliqueInfo &C = P.cl[top.first];
+            if (top.second < C.children.size()) {
+                const int32_t ch = C.children[top.second++];
+                plain_message(ch, top.first, ch);
+                st2.push_back({ch, 0});
+            } else {
+                st2.pop_back();
+            }
+        }
+    }
+    {
+        // read-out: totals of every calibrated table, then normalize in place
+        const int32_t t0 = (int32_t)P.tasks.size();
+        const int32_t m0 = (int32_t)P.msgs.size();
+        for (int32_t c = 0; c < nc; ++c) {
+            const int32_t view = P.cl[c].total_view;
+            const int32_t it = add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_NONE, 0, {}, -1, view, 0, bytes);
+            const int64_t poff = add_partial(item_nsplit(P, it));
+            P.items[it].partial_off = poff;
+            JtMsg m;
+            std::memset(&m, 0, sizeof(m));
+            m.kind = JT_MSG_PLAIN_TOTAL;
+            m.edge = -1;
+            m.from = c;
+            m.to = (c == P.root) ? -2 : -1;   // -2 marks the root: log Z is read there
+            m.ssize = 1;
+            m.nsplit = P.items[it].nsplit;
+            m.partial_off = poff;
+            P.msgs.push_back(m);
+        }
+        P.plain.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        P.plain.push_back({0, m0, (int32_t)P.msgs.size() - m0});
+        const int32_t t1 = (int32_t)P.tasks.size();
+        for (int32_t c = 0; c < nc; ++c)
+            add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_OUT, P.cl[c].out_off, {}, c, -1, 0, bytes);
+        P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
+    }
+    P.bytes_plain = bytes;
+    if (P.partial_stride > std::numeric_limits<int32_t>::max() * int64_t(4))
+        return fail(err, JT_E_TOO_LARGE, "partial region too large");
+
+    // ---------------- workspace layout ----------------
+    P.lam_stride = align_up(3 * (int64_t)nc + 1, 32);
+    P.scale_stride = align_up(nc, kAlignFloats);
+    P.ev_idx_stride = align_up((int64_t)nc + 1, kAlignFloats);
+    P.ev_ent_stride = align_up(2 * (int64_t)nv + 1, 16);
+    size_t off = 0;
+    auto region = [&](size_t bytes_) {
+        const size_t o = off;
+        off = (size_t)align_up((int64_t)(off + bytes_), 256);
+        return o;
+    };
+    const size_t S = (size_t)P.n_slots;
+    P.off_meta = region(P.meta.size() * sizeof(int32_t));
+    P.off_views = region(P.views.size() * sizeof(JtView));
+    P.off_gathers = region(std::max<size_t>(1, P.gathers.size()) * sizeof(JtGather));
+    P.off_items = region(P.items.size() * sizeof(JtItem));
+    P.off_tasks = region(P.tasks.size() * sizeof(JtTask));
+    P.off_msgs = region(P.msgs.size() * sizeof(JtMsg));
+    P.off_child = region(std::max<size_t>(1, P.child_edges.size()) * sizeof(int32_t));
+    P.off_init = region((size_t)P.init_floats * sizeof(float));
+    P.off_coll = region(S * (size_t)P.coll_stride * sizeof(float));
+    P.off_out = region(S * (size_t)P.out_stride * sizeof(float));
+    P.off_sep = region(S * (size_t)P.sep_stride * sizeof(float));
+    P.off_partial = region(S * (size_t)P.partial_stride * sizeof(float));
+    P.off_lam = region(S * (size_t)P.lam_stride * sizeof(double));
+    P.off_scale = region(S * (size_t)P.scale_stride * sizeof(float));
+    P.off_flag = region(S * sizeof(int32_t));
+    P.off_ev_idx = region(S * (size_t)P.ev_idx_stride * sizeof(int32_t));
+    P.off_ev_ent = region(S * (size_t)P.ev_ent_stride * sizeof(JtEv));
+    P.total_bytes = off;
+    std::string why;
+    if (!verify_plan(P, why)) return fail(err, JT_E_ARG, why);
+    return JT_OK;
+}
+
+void evidence_tables(const Plan &P, const std::vector<int32_t> &vars, const std::vector<int32_t> &states,
+                     int32_t *idx, JtEv *ent) {
+    const int32_t nc = P.n_cliques;
+    std::vector<std::vector<JtEv>> per(nc);
+    std::vector<int32_t> seen(P.n_vars, 0);
+    for (size_t a = 0; a < vars.size(); ++a) {
+        const int32_t v = vars[a], s = states[a];
+        if (seen[v]) continue;   // repeats carry the same state (checked by the caller)
+        seen[v] = 1;
+        const int32_t c = P.home[v];
+        if (c < 0) continue;
+        for (const VDigit &d : P.cl[c].digits) {
+            if (d.var != v || d.card == 1) continue;
+            JtEv e;
+            e.outer = d.outer ? 1 : 0;
+            e.stride = (int32_t)(d.outer ? d.ostride : d.stride);
+            e.card = d.card;
+            e.digit = (int32_t)((s / d.w) % d.card);
+            per[c].push_back(e);
+        }
+    }
+    int32_t k = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        idx[c] = k;
+        for (const JtEv &e : per[c]) ent[k++] = e;
+    }
+    idx[nc] = k;
+}
+
+void expand_map(const Plan &P, int32_t view, int32_t *out) {
+    const JtView &V = P.views[view];
+    const CliqueInfo &C = P.cl[V.clique];
+    const int32_t *jin = P.meta.data() + V.jin_off;
+    const int32_t *jout = P.meta.data() + V.jout_off;
+    for (int64_t o = 0; o < C.n_tiles; ++o)
+        for (int64_t i = 0; i < C.T; ++i) out[o * C.T + i] = jin[i] + jout[o];
+}
+
+}  // namespace jt

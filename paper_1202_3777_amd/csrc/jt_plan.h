@@ -1,0 +1,99 @@
+// jt_plan.h -- host-side compiled junction tree (C++ only, no HIP).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "jt.h"
+#include "jt_internal.h"
+
+namespace jt {
+
+// A digit of the table index.  A variable is one digit, or two when the
+// tile boundary falls inside it (high digit outer, low digit inner); the
+// variable's state is sum(sub_digit * w).
+struct VDigit {
+    int32_t var;
+    int32_t card;
+    int64_t stride;   // in table entries
+    int64_t w;        // weight of this digit inside the variable's state
+    bool outer;
+    int64_t ostride;  // in tiles (outer digits only)
+};
+
+struct CliqueInfo {
+    std::vector<int32_t> vars;       // listed order = table layout
+    int64_t size = 0;
+    std::vector<VDigit> digits;
+    int32_t T = 1, vec = 1;
+    int64_t n_tiles = 1;
+    int64_t init_off = 0, coll_off = -1, out_off = 0;
+    int32_t height = 0, depth = 0;
+    std::vector<int32_t> children;   // ascending id
+    int32_t total_view = -1;
+    int32_t parent_view = -1;        // this clique through its parent separator
+};
+
+struct EdgeInfo {                    // edge (c, parent[c]); id = c
+    std::vector<int32_t> vars;       // ascending id
+    std::vector<int64_t> sst;        // separator stride of each variable
+    int64_t ssize = 1;
+    int32_t sepc_off = 0, sepd_off = 0;
+    int32_t view_child = -1, view_parent = -1;
+};
+
+struct Launch {
+    int32_t is_pass;        // 1 = pass kernel over tasks, 0 = finalize over msgs
+    int32_t begin, count;   // tasks or msgs (per slot)
+};
+
+struct Plan {
+    // tree
+    int32_t n_vars = 0, n_cliques = 0, n_slots = 1, root = -1;
+    std::vector<int32_t> card, parent;
+    std::vector<CliqueInfo> cl;
+    std::vector<EdgeInfo> edge;
+    std::vector<int32_t> home;       // lowest clique id holding each variable
+    int32_t height = 0, depth = 0;
+
+    // device metadata (host copies)
+    std::vector<int32_t> meta;
+    std::vector<JtView> views;
+    std::vector<JtGather> gathers;
+    std::vector<JtItem> items;
+    std::vector<JtTask> tasks;
+    std::vector<JtMsg> msgs;
+    std::vector<int32_t> child_edges;
+    std::vector<Launch> fused;       // launch list of one fused propagation
+    std::vector<Launch> plain;       // launch list of one one-at-a-time propagation
+    int32_t plain_reset_task_begin = 0, plain_reset_task_count = 0;
+
+    // per-slot region sizes (elements)
+    int64_t init_floats = 0, coll_stride = 0, out_stride = 0, sep_stride = 0,
+            partial_stride = 0, lam_stride = 0, scale_stride = 0, ev_idx_stride = 0,
+            ev_ent_stride = 0;
+    // byte offsets of every region inside the workspace
+    size_t off_meta = 0, off_views = 0, off_gathers = 0, off_items = 0, off_tasks = 0,
+           off_msgs = 0, off_child = 0, off_init = 0, off_coll = 0, off_out = 0, off_sep = 0,
+           off_partial = 0, off_lam = 0, off_scale = 0, off_flag = 0, off_ev_idx = 0,
+           off_ev_ent = 0, total_bytes = 0;
+
+    // statistics
+    int64_t total_entries = 0, entries_per_sweep = 0;
+    int64_t bytes_fused = 0, bytes_plain = 0;   // per slot
+};
+
+// Build the plan; returns JT_OK or an error code with `err` filled in.
+jt_status compile_plan(const jt_tree_desc *desc, Plan &plan, std::string &err);
+
+// Evidence of one slot as device digit conditions (host side).
+// idx gets n_cliques + 1 offsets into ent; ent gets the conditions.
+void evidence_tables(const Plan &plan, const std::vector<int32_t> &vars,
+                     const std::vector<int32_t> &states, int32_t *idx, JtEv *ent);
+
+// Separator index of every entry of clique `c` seen through view `v`
+// (reconstructed from the factored tables).
+void expand_map(const Plan &plan, int32_t view, int32_t *out);
+
+}  // namespace jt

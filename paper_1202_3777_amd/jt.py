@@ -1,0 +1,287 @@
+"""Python binding of the junction-tree message engine (``include/jt.h``).
+
+Argument marshalling only: every step of belief propagation runs in the HIP
+kernels of ``libjt.so``.  The functions mirror the C ABI one to one;
+``JunctionTree`` adds torch-owned device memory and stream handling.  The
+binding raises if the built library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjt.so")
+
+JT_OK = 0
+JT_E_ARG = -1
+JT_E_NOT_JUNCTION_TREE = -2
+JT_E_TOO_LARGE = -3
+JT_E_NO_MEM = -4
+JT_E_HIP = -5
+JT_E_ZERO_EVIDENCE = -6
+JT_E_STATE = -7
+
+JT_MODE_FUSED = 0
+JT_MODE_GRAPH = 1
+JT_MODE_PLAIN = 2
+MODES = {"fused": JT_MODE_FUSED, "graph": JT_MODE_GRAPH, "plain": JT_MODE_PLAIN}
+
+JT_Q_N_SLOTS = 0
+JT_Q_TOTAL_ENTRIES = 1
+JT_Q_TABLE_SIZE = 2
+JT_Q_SEP_SIZE = 3
+JT_Q_ENTRIES_PER_SWEEP = 4
+JT_Q_BYTES_FUSED = 5
+JT_Q_BYTES_PLAIN = 6
+JT_Q_N_LAUNCHES_FUSED = 7
+JT_Q_N_LAUNCHES_PLAIN = 8
+JT_Q_HEIGHT = 9
+JT_Q_DEPTH = 10
+
+EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_marginal",
+            "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
+            "jt_free", "jt_last_error"]
+
+
+class JTError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what} failed with status {code}: {msg}")
+        self.code = code
+
+
+class jt_tree_desc(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("card", ctypes.POINTER(ctypes.c_int32)),
+                ("n_cliques", ctypes.c_int32), ("clique_off", ctypes.POINTER(ctypes.c_int64)),
+                ("clique_vars", ctypes.POINTER(ctypes.c_int32)), ("parent", ctypes.POINTER(ctypes.c_int32)),
+                ("n_slots", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1202_3777_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    V, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    P32, P64, PF, PD = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double))
+    lib.jt_compile_index_maps.argtypes = [ctypes.POINTER(jt_tree_desc), ctypes.POINTER(V), ctypes.POINTER(SZ)]
+    lib.jt_bind.argtypes = [V, V, SZ, V, V]
+    lib.jt_set_evidence.argtypes = [V, I32, I32, P32, P32]
+    lib.jt_propagate.argtypes = [V, I32]
+    lib.jt_marginal.argtypes = [V, I32, I32, V, PD]
+    lib.jt_marginals_all.argtypes = [V, I32, V, PD]
+    lib.jt_get_index_map.argtypes = [V, I32, I32, P32]
+    lib.jt_get_mu_lists.argtypes = [V, I32, I32, P32]
+    lib.jt_query.argtypes = [V, I32, I64, P64]
+    lib.jt_profile.argtypes = [V, I32, PD, PD, P32, P32]
+    for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_marginal",
+              "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile"):
+        getattr(lib, f).restype = I32
+    lib.jt_free.argtypes = [V]
+    lib.jt_free.restype = None
+    lib.jt_last_error.argtypes = []
+    lib.jt_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != JT_OK:
+        raise JTError(rc, what, load().jt_last_error().decode())
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+# --------------------------------------------------------------------------
+# one-to-one wrappers of the C ABI
+
+def jt_compile_index_maps(card, clique_off, clique_vars, parent, n_slots: int = 1):
+    """Returns (handle, device_bytes, keepalive)."""
+    lib = load()
+    card = np.ascontiguousarray(card, dtype=np.int32)
+    off = np.ascontiguousarray(clique_off, dtype=np.int64)
+    cv = np.ascontiguousarray(clique_vars, dtype=np.int32)
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    d = jt_tree_desc(int(card.shape[0]), _p(card, ctypes.c_int32), int(par.shape[0]), _p(off, ctypes.c_int64),
+                     _p(cv, ctypes.c_int32), _p(par, ctypes.c_int32), int(n_slots))
+    h = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    _check(lib.jt_compile_index_maps(ctypes.byref(d), ctypes.byref(h), ctypes.byref(nbytes)),
+           "jt_compile_index_maps")
+    return h, int(nbytes.value)
+
+
+def jt_bind(h, workspace_ptr: int, nbytes: int, init_ptr: int, stream_ptr: int):
+    _check(load().jt_bind(h, ctypes.c_void_p(workspace_ptr), nbytes, ctypes.c_void_p(init_ptr),
+                          ctypes.c_void_p(stream_ptr)), "jt_bind")
+
+
+def jt_set_evidence(h, slot: int, vars: Sequence[int], states: Sequence[int]):
+    v = np.ascontiguousarray(vars, dtype=np.int32)
+    s = np.ascontiguousarray(states, dtype=np.int32)
+    if v.shape != s.shape:
+        raise ValueError("vars and states differ in length")
+    _check(load().jt_set_evidence(h, int(slot), int(v.shape[0]), _p(v, ctypes.c_int32), _p(s, ctypes.c_int32)),
+           "jt_set_evidence")
+
+
+def jt_propagate(h, mode: int = JT_MODE_FUSED):
+    _check(load().jt_propagate(h, int(mode)), "jt_propagate")
+
+
+def jt_marginal(h, slot: int, clique: int, out_ptr: Optional[int]) -> float:
+    lz = ctypes.c_double()
+    _check(load().jt_marginal(h, int(slot), int(clique), ctypes.c_void_p(out_ptr or 0), ctypes.byref(lz)),
+           "jt_marginal")
+    return lz.value
+
+
+def jt_marginals_all(h, slot: int, out_ptr: Optional[int]) -> float:
+    lz = ctypes.c_double()
+    _check(load().jt_marginals_all(h, int(slot), ctypes.c_void_p(out_ptr or 0), ctypes.byref(lz)),
+           "jt_marginals_all")
+    return lz.value
+
+
+def jt_query(h, what: int, arg: int = 0) -> int:
+    out = ctypes.c_int64()
+    _check(load().jt_query(h, int(what), int(arg), ctypes.byref(out)), "jt_query")
+    return int(out.value)
+
+
+def jt_get_index_map(h, child: int, side: int, table_size: int) -> np.ndarray:
+    out = np.empty(int(table_size), dtype=np.int32)
+    _check(load().jt_get_index_map(h, int(child), int(side), _p(out, ctypes.c_int32)), "jt_get_index_map")
+    return out
+
+
+def jt_get_mu_lists(h, child: int, side: int, table_size: int) -> np.ndarray:
+    out = np.empty(int(table_size), dtype=np.int32)
+    _check(load().jt_get_mu_lists(h, int(child), int(side), _p(out, ctypes.c_int32)), "jt_get_mu_lists")
+    return out
+
+
+def jt_profile(h, mode: int = JT_MODE_FUSED):
+    """(pass_ms, finalize_ms, n_pass, n_finalize) of one propagation."""
+    pm, fm = ctypes.c_double(), ctypes.c_double()
+    npass, nfin = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().jt_profile(h, int(mode), ctypes.byref(pm), ctypes.byref(fm), ctypes.byref(npass),
+                             ctypes.byref(nfin)), "jt_profile")
+    return pm.value, fm.value, npass.value, nfin.value
+
+
+def jt_free(h):
+    if h is not None and h.value:
+        load().jt_free(h)
+
+
+def jt_last_error() -> str:
+    return load().jt_last_error().decode()
+
+
+# --------------------------------------------------------------------------
+
+class JunctionTreePlan:
+    """A compiled tree (host side only): index maps and schedule facts."""
+
+    def __init__(self, card, clique_off, clique_vars, parent, n_slots: int = 1):
+        self.card = np.ascontiguousarray(card, dtype=np.int32)
+        self.clique_off = np.ascontiguousarray(clique_off, dtype=np.int64)
+        self.clique_vars = np.ascontiguousarray(clique_vars, dtype=np.int32)
+        self.parent = np.ascontiguousarray(parent, dtype=np.int32)
+        self.n_cliques = int(self.parent.shape[0])
+        self.n_slots = int(n_slots)
+        self.handle, self.device_bytes = jt_compile_index_maps(self.card, self.clique_off, self.clique_vars,
+                                                               self.parent, n_slots)
+        self.table_size = np.asarray([jt_query(self.handle, JT_Q_TABLE_SIZE, c) for c in range(self.n_cliques)],
+                                     dtype=np.int64)
+        self.table_off = np.concatenate([[0], np.cumsum(self.table_size)]).astype(np.int64)
+
+    @classmethod
+    def from_instance(cls, inst, n_slots: Optional[int] = None):
+        return cls(inst.card, inst.clique_off, inst.clique_vars, inst.parent,
+                   n_slots if n_slots is not None else max(1, inst.n_slots))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None:
+            jt_free(h)
+            self.handle = None
+
+    def query(self, what: int, arg: int = 0) -> int:
+        return jt_query(self.handle, what, arg)
+
+    def index_map(self, child: int, side: int) -> np.ndarray:
+        c = child if side == 0 else int(self.parent[child])
+        return jt_get_index_map(self.handle, child, side, int(self.table_size[c]))
+
+    def mu_lists(self, child: int, side: int) -> np.ndarray:
+        c = child if side == 0 else int(self.parent[child])
+        out = jt_get_mu_lists(self.handle, child, side, int(self.table_size[c]))
+        return out.reshape(self.query(JT_Q_SEP_SIZE, child), -1)
+
+
+class JunctionTree(JunctionTreePlan):
+    """A compiled tree bound to torch-owned device memory on one stream."""
+
+    def __init__(self, card, clique_off, clique_vars, parent, potentials: np.ndarray, n_slots: int = 1,
+                 device: str = "cuda", stream=None):
+        import torch
+        super().__init__(card, clique_off, clique_vars, parent, n_slots)
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(self.device_bytes, dtype=torch.uint8, device=self.device)
+        pot = np.ascontiguousarray(potentials, dtype=np.float32)
+        if pot.shape[0] != int(self.table_off[-1]):
+            raise ValueError("potentials do not match the table sizes")
+        init = torch.from_numpy(pot).to(self.device)
+        jt_bind(self.handle, self.workspace.data_ptr(), self.device_bytes, init.data_ptr(),
+                self.stream.cuda_stream)
+        self.stream.synchronize()      # the copy out of `init` is done; it may go
+        del init
+
+    @classmethod
+    def from_instance(cls, inst, n_slots: Optional[int] = None, **kw):
+        t = cls(inst.card, inst.clique_off, inst.clique_vars, inst.parent, inst.potentials,
+                n_slots if n_slots is not None else max(1, inst.n_slots), **kw)
+        for s, (v, st) in enumerate(inst.evidence[:t.n_slots]):
+            t.set_evidence(s, v, st)
+        return t
+
+    def set_evidence(self, slot: int, vars: Sequence[int], states: Sequence[int]):
+        jt_set_evidence(self.handle, slot, vars, states)
+
+    def propagate(self, mode: str = "fused"):
+        jt_propagate(self.handle, MODES[mode])
+
+    def profile(self, mode: str = "fused"):
+        return jt_profile(self.handle, MODES[mode])
+
+    def marginal(self, slot: int, clique: int) -> Tuple[np.ndarray, float]:
+        out = np.empty(int(self.table_size[clique]), dtype=np.float32)
+        lz = jt_marginal(self.handle, slot, clique, out.ctypes.data)
+        return out, lz
+
+    def marginals_all(self, slot: int):
+        out = np.empty(int(self.table_off[-1]), dtype=np.float32)
+        lz = jt_marginals_all(self.handle, slot, out.ctypes.data)
+        return out, lz
+
+    def marginals_all_device(self, slot: int):
+        out = self.torch.empty(int(self.table_off[-1]), dtype=self.torch.float32, device=self.device)
+        lz = jt_marginals_all(self.handle, slot, out.data_ptr())
+        return out, lz

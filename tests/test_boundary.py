@@ -1,0 +1,166 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+  * the library loads and exports every function include/jt.h declares;
+  * the precomputed cluster-separator mappings are bit-exact against the
+    oracle's state-string scan (CSM single table and the paper's mu lists),
+    and reproduce Fig. 2;
+  * invalid trees, evidence and call orders return the documented status;
+  * schedule facts (entries per sweep, algorithmic bytes, launch counts).
+"""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1202_3777_amd import jt
+from paper_1202_3777_amd.instances import from_arrays, make_instance
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "jt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(jt_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = jt.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(jt.EXPORTED) == names
+
+
+def test_fig2_maps_from_library():
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "fig2_maps.json")))
+    inst = from_arrays(g["card"], [g["X_i"], g["X_k"]], [-1, 0])
+    plan = jt.JunctionTreePlan.from_instance(inst)
+    assert plan.mu_lists(1, 1).tolist() == g["mu_X_i"]
+    assert plan.mu_lists(1, 0).tolist() == g["mu_X_k"]
+
+
+@pytest.mark.parametrize("name,seed,kw", [
+    ("c1", 0, {}), ("c1", 1, {}), ("c4", 0, {}), ("c4", 2, {}),
+    ("c2", 0, dict(n_cliques=6)), ("c3", 0, dict(n_cliques=6)), ("c3", 1, dict(n_cliques=5)),
+])
+def test_index_maps_bit_exact(name, seed, kw):
+    inst = make_instance(name, seed, **kw)
+    plan = jt.JunctionTreePlan.from_instance(inst)
+    ref = oracle.Plan.from_instance(inst)
+    for c in range(inst.n_cliques):
+        if inst.parent[c] < 0:
+            continue
+        assert plan.query(jt.JT_Q_SEP_SIZE, c) == ref.sep_size(c)
+        for side in (0, 1):
+            assert np.array_equal(plan.index_map(c, side), ref.csm_map(c, side))
+            assert np.array_equal(plan.mu_lists(c, side), ref.mu(c, side))
+
+
+def test_index_maps_odd_shapes():
+    # prime cardinality above the tile limit (tile of one entry), a variable
+    # of cardinality 1, and a clique joined by an empty separator
+    card = [257, 2, 1, 3, 5, 7]
+    cliques = [[0, 1], [1, 2, 3], [3, 4, 5], [5]]
+    parent = [-1, 0, 1, 2]
+    inst = from_arrays(card, cliques, parent)
+    plan = jt.JunctionTreePlan.from_instance(inst)
+    ref = oracle.Plan.from_instance(inst)
+    for c in (1, 2, 3):
+        for side in (0, 1):
+            assert np.array_equal(plan.index_map(c, side), ref.csm_map(c, side))
+    inst2 = from_arrays([2, 3, 4], [[0, 1], [2]], [-1, 0])   # empty separator
+    p2 = jt.JunctionTreePlan.from_instance(inst2)
+    assert p2.query(jt.JT_Q_SEP_SIZE, 1) == 1
+    assert np.array_equal(p2.index_map(1, 1), np.zeros(6, np.int32))
+
+
+def _compile(card, cliques, parent, n_slots=1):
+    off = np.concatenate([[0], np.cumsum([len(c) for c in cliques])]).astype(np.int64)
+    flat = np.array([v for c in cliques for v in c], dtype=np.int32)
+    return jt.jt_compile_index_maps(np.array(card, np.int32), off, flat, np.array(parent, np.int32), n_slots)
+
+
+@pytest.mark.parametrize("card,cliques,parent,n_slots,code", [
+    ([2, 2, 2], [[0, 1], [1, 2]], [-1, -1], 1, jt.JT_E_NOT_JUNCTION_TREE),          # two roots
+    ([2, 2, 2], [[0, 1], [1, 2]], [1, 0], 1, jt.JT_E_NOT_JUNCTION_TREE),            # cycle
+    ([2, 2, 2], [[0, 1], [1, 2], [2, 0]], [-1, 0, 1], 1, jt.JT_E_NOT_JUNCTION_TREE),  # running intersection
+    ([2, 2, 2], [[0, 0], [0, 1]], [-1, 0], 1, jt.JT_E_ARG),                         # repeated variable
+    ([2, 2, 2], [[0, 5], [0, 1]], [-1, 0], 1, jt.JT_E_ARG),                         # variable out of range
+    ([2, 0, 2], [[0, 1], [1, 2]], [-1, 0], 1, jt.JT_E_ARG),                         # cardinality 0
+    ([2, 2, 2], [[0, 1], [1, 2]], [-1, 9], 1, jt.JT_E_NOT_JUNCTION_TREE),           # parent out of range
+    ([2, 2, 2], [[0, 1], [1, 2]], [-1, 0], 0, jt.JT_E_ARG),                         # no slots
+    ([3000, 3000, 3000], [[0, 1, 2]], [-1], 1, jt.JT_E_TOO_LARGE),                  # 2.7e10 entries
+])
+def test_compile_errors(card, cliques, parent, n_slots, code):
+    with pytest.raises(jt.JTError) as ei:
+        _compile(card, cliques, parent, n_slots)
+    assert ei.value.code == code
+    assert jt.jt_last_error() != ""
+
+
+def test_call_order_and_argument_errors():
+    inst = make_instance("c1", 0)
+    plan = jt.JunctionTreePlan.from_instance(inst)
+    h = plan.handle
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_propagate(h, jt.JT_MODE_FUSED)          # not bound
+    assert ei.value.code == jt.JT_E_STATE
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_marginal(h, 0, 0, None)                 # nothing propagated
+    assert ei.value.code == jt.JT_E_STATE
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_bind(h, 0, plan.device_bytes, 0, 0)     # NULL workspace
+    assert ei.value.code == jt.JT_E_ARG
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_bind(h, 4096, 16, 8192, 0)              # workspace too small (checked before any copy)
+    assert ei.value.code == jt.JT_E_NO_MEM
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_bind(h, 4100, plan.device_bytes, 8192, 0)   # misaligned
+    assert ei.value.code == jt.JT_E_ARG
+    for slot, vs, st in ((1, [0], [0]), (0, [999], [0]), (0, [0], [2]), (0, [3, 3], [0, 1]), (-1, [], [])):
+        with pytest.raises(jt.JTError) as ei:
+            jt.jt_set_evidence(h, slot, vs, st)
+        assert ei.value.code == jt.JT_E_ARG
+    jt.jt_set_evidence(h, 0, [3, 3], [1, 1])          # repeated, same state: fine
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_get_index_map(h, int(np.where(inst.parent < 0)[0][0]), 0, 32)   # the root has no separator
+    assert ei.value.code == jt.JT_E_ARG
+    with pytest.raises(jt.JTError):
+        jt.jt_query(h, 99)
+
+
+@pytest.mark.parametrize("name,kw", [("c1", {}), ("c4", dict(n_slots=1)), ("c2", dict(n_cliques=9))])
+def test_schedule_facts(name, kw):
+    inst = make_instance(name, 1, **kw)
+    plan = jt.JunctionTreePlan.from_instance(inst)
+    sizes = np.diff(inst.table_off)
+    eps = sum(int(sizes[c] + sizes[inst.parent[c]]) for c in range(inst.n_cliques) if inst.parent[c] >= 0)
+    assert plan.query(jt.JT_Q_ENTRIES_PER_SWEEP) == eps
+    assert plan.query(jt.JT_Q_TOTAL_ENTRIES) == int(sizes.sum())
+    # fused schedule bytes: every clique read once in collect (plus a write of
+    # the absorbed table when it has children); in distribute a leaf reads its
+    # initial table and writes its posterior, a clique with k children reads
+    # its absorbed table k times and writes its posterior once
+    kids = [np.count_nonzero(inst.parent == c) for c in range(inst.n_cliques)]
+    exp = 0
+    for c in range(inst.n_cliques):
+        b = 4 * int(sizes[c])
+        exp += b + (b if kids[c] else 0)
+        exp += 2 * b if kids[c] == 0 else (kids[c] + 1) * b
+    assert plan.query(jt.JT_Q_BYTES_FUSED) == exp
+    # one-at-a-time: reset copy, marginalize + in-place scatter per message,
+    # total + in-place normalize per clique
+    exp_p = sum(8 * int(s) for s in sizes)
+    for c in range(inst.n_cliques):
+        p = inst.parent[c]
+        if p >= 0:
+            exp_p += 4 * int(sizes[c]) + 8 * int(sizes[p]) + 4 * int(sizes[p]) + 8 * int(sizes[c])
+    exp_p += sum(12 * int(s) for s in sizes)
+    assert plan.query(jt.JT_Q_BYTES_PLAIN) == exp_p
+    n = inst.n_cliques
+    assert plan.query(jt.JT_Q_N_LAUNCHES_PLAIN) == 2 + 3 * 2 * (n - 1) + 3
