@@ -243,12 +243,15 @@ class JunctionTree(JunctionTreePlan):
         super().__init__(card, clique_off, clique_vars, parent, n_slots)
         self.torch = torch
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own: the legacy default stream cannot be captured
+        # into a graph (default priority, see the stream rules of the box)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.workspace = torch.empty(self.device_bytes, dtype=torch.uint8, device=self.device)
         pot = np.ascontiguousarray(potentials, dtype=np.float32)
         if pot.shape[0] != int(self.table_off[-1]):
             raise ValueError("potentials do not match the table sizes")
         init = torch.from_numpy(pot).to(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         jt_bind(self.handle, self.workspace.data_ptr(), self.device_bytes, init.data_ptr(),
                 self.stream.cuda_stream)
         self.stream.synchronize()      # the copy out of `init` is done; it may go
