@@ -181,6 +181,11 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     if (e == hipSuccess) e = up(P.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(JtTask));
     if (e == hipSuccess) e = up(P.off_msgs, P.msgs.data(), P.msgs.size() * sizeof(JtMsg));
     if (e == hipSuccess) e = up(P.off_child, P.child_edges.data(), P.child_edges.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(P.off_ftasks, P.ftasks.data(), P.ftasks.size() * sizeof(JtFTask));
+    // finalize arrival counters start at zero; each finalize's last block
+    // resets its counter, so no clearing is needed between propagations
+    if (e == hipSuccess)
+        e = hipMemsetAsync(t->ws + P.off_fcnt, 0, (size_t)P.n_slots * P.fcnt_stride * sizeof(int32_t), s);
     // initial tables into the aligned layout, one copy per clique
     int64_t src_off = 0;
     for (int32_t c = 0; c < P.n_cliques && e == hipSuccess; ++c) {
@@ -199,6 +204,11 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     d.tasks = region<JtTask>(t, P.off_tasks);
     d.msgs = region<JtMsg>(t, P.off_msgs);
     d.child_edges = region<int32_t>(t, P.off_child);
+    d.ftasks = region<JtFTask>(t, P.off_ftasks);
+    d.fsig = reinterpret_cast<double *>(t->ws + P.off_fsig);
+    d.fcnt = reinterpret_cast<int32_t *>(t->ws + P.off_fcnt);
+    d.fsig_stride = P.fsig_stride;
+    d.fcnt_stride = P.fcnt_stride;
     d.init = region<float>(t, P.off_init);
     d.coll = reinterpret_cast<float *>(t->ws + P.off_coll);
     d.out = reinterpret_cast<float *>(t->ws + P.off_out);

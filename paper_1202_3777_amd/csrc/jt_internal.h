@@ -20,7 +20,7 @@
 #define JT_BLOCK 256
 #define JT_WAVES_PER_BLOCK (JT_BLOCK / JT_WAVE)
 #define JT_TILE_MAX 256           /* one wave covers a tile: 64 lanes x 4 entries */
-#define JT_NG_REG 8               /* gathers whose Jin values live in registers */
+#define JT_NG_REG 4               /* gathers whose Jin values live in registers */
 #define JT_LDS_RATIO_FLOATS 8192  /* 32 KiB of LDS for staged ratio tables */
 #define JT_UNROLL 4               /* tiles in flight per wave */
 
@@ -44,6 +44,7 @@ typedef struct {
     int32_t sep_off;  // float offset of the table inside the per-slot separator region
     int32_t ssize;
     int32_t lds_off;  // float offset of its LDS copy, -1 = read from global memory
+    int32_t jin_off, jout_off;   // the view's Jin / Jout tables (int32 meta offsets)
 } JtGather;
 
 enum { JT_SRC_INIT = 0, JT_SRC_COLL = 1, JT_SRC_OUT = 2 };
@@ -65,6 +66,10 @@ typedef struct {
     int32_t nsplit;             // groups per kept-outer configuration
     int32_t n_groups;
     int64_t partial_off;        // float offset in the per-slot partial region
+    // the output view's reduction tables, copied here to keep the kernel
+    // prologue short (meta offsets stay below 2^30)
+    int32_t o_kout_tile, o_kout_j, o_rout_tile, o_perm, o_clsj;
+    int32_t o_n_rout, o_n_cls, o_m_in, o_ssize, pad;
 } JtItem;
 
 // A block's share of an item: groups [g0, g1), spread over the block's waves.
@@ -90,7 +95,14 @@ typedef struct {
     int64_t partial_off;
     int32_t child_base, n_children;  // children edges of `from` (collect log-scale sum)
     int32_t sepc_off, sepd_off;      // separator tables in the per-slot region
+    int32_t fbase, nfb;              // finalize blocks: per-slot sigma scratch index, count
 } JtMsg;
+
+// A block's share of one message's finalize: separator entries [j0, j1),
+// jc columns by JT_BLOCK / jc split rows; block b of nb for the message.
+typedef struct {
+    int32_t msg, j0, j1, jc, b, nb, pad0, pad1;
+} JtFTask;
 
 // One digit condition of hard evidence: entry kept iff
 // (index / stride) % card == digit, index being the tile index for outer
@@ -114,6 +126,7 @@ typedef struct {
     const JtItem *items;
     const JtTask *tasks;
     const JtMsg *msgs;
+    const JtFTask *ftasks;
     const int32_t *child_edges;
     const float *init;
     float *coll;
@@ -123,9 +136,12 @@ typedef struct {
     double *lam;
     float *scale;
     int32_t *flag;
+    double *fsig;                  // per-slot block sums of the finalize
+    int32_t *fcnt;                 // per-slot arrival counters, one per message
     const int32_t *ev_idx;
     const JtEv *ev_ent;
     int64_t coll_stride, out_stride, sep_stride, partial_stride;
     int64_t lam_stride, scale_stride, ev_idx_stride, ev_ent_stride;
+    int64_t fsig_stride, fcnt_stride;
     int32_t n_cliques, pad;
 } JtDev;

@@ -36,18 +36,37 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 struct GatherReg {
-    int64_t jout_off;
-    int32_t off;      // LDS float offset, or float offset in the slot's separator region
+    int32_t jout_off;  // Jout table of the gather's view (meta offsets stay below 2^30)
+    int32_t off;       // LDS float offset, or float offset in the slot's separator region
     int32_t in_lds;
 };
 
+// Per-tile context of the tiles a wave has in flight.
 template <int VEC>
-__device__ __forceinline__ void pass_body(const JtDev &d, const JtItem &it, const JtTask &task, int slot,
-                                          const float *__restrict__ lds_ratio, float *__restrict__ lds_red) {
+struct TileBatch {
+    int o[JT_UNROLL];
+    float x[JT_UNROLL][4];
+};
+
+// Strides of the per-slot regions (values only, passed by value).
+struct PassStrides {
+    int64_t coll, out, sep, partial, scale, ev_idx, ev_ent;
+};
+
+template <int VEC>
+__device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, int slot,
+                                          const JtGather *__restrict__ gathers, const int32_t *__restrict__ meta,
+                                          const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
+                                          const float *__restrict__ init, float *__restrict__ coll,
+                                          float *__restrict__ out, const float *__restrict__ sep,
+                                          const float *__restrict__ scale_arr, float *__restrict__ partial,
+                                          const PassStrides &st, const float *__restrict__ lds_ratio,
+                                          float *__restrict__ lds_red) {
     const int lane = threadIdx.x & (JT_WAVE - 1);
-    const int wave = threadIdx.x / JT_WAVE;
+    // wave-uniform by construction; saying so lets the compiler keep the
+    // group / tile bookkeeping and the metadata loads on the scalar unit
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / JT_WAVE);
     const int T = it.T;
-    const int32_t *__restrict__ meta = d.meta;
 
     int pos[4];
     bool valid[4];
@@ -62,32 +81,31 @@ __device__ __forceinline__ void pass_body(const JtDev &d, const JtItem &it, cons
     const int ngr = ng < JT_NG_REG ? ng : JT_NG_REG;
     GatherReg gr[JT_NG_REG];
     int jin[JT_NG_REG][4];
-    const float *__restrict__ sep_slot = d.sep + (int64_t)slot * d.sep_stride;
+    const float *__restrict__ sep_slot = sep + (int64_t)slot * st.sep;
 #pragma unroll
     for (int g = 0; g < JT_NG_REG; ++g) {
+        gr[g].jout_off = 0;
+        gr[g].in_lds = 0;
+        gr[g].off = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) jin[g][q] = 0;
         if (g < ngr) {
-            const JtGather G = d.gathers[it.gather_base + g];
-            const JtView V = d.views[G.view];
-            gr[g].jout_off = V.jout_off;
+            const JtGather G = gathers[it.gather_base + g];
+            gr[g].jout_off = G.jout_off;
             gr[g].in_lds = G.lds_off >= 0;
             gr[g].off = G.lds_off >= 0 ? G.lds_off : G.sep_off;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) jin[g][q] = valid[q] ? meta[V.jin_off + pos[q]] : 0;
-        } else {
-            gr[g].jout_off = 0;
-            gr[g].in_lds = 0;
-            gr[g].off = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) jin[g][q] = 0;
+            for (int q = 0; q < 4; ++q)
+                if (valid[q]) jin[g][q] = meta[G.jin_off + pos[q]];
         }
     }
 
     // evidence: inner digits give a per-lane mask, outer digits zero whole tiles
     bool keep[4] = {true, true, true, true};
     int ev0 = 0, ev1 = 0;
-    const JtEv *__restrict__ evs = d.ev_ent + (int64_t)slot * d.ev_ent_stride;
+    const JtEv *__restrict__ evs = ev_ent + (int64_t)slot * st.ev_ent;
     if (it.ev) {
-        const int32_t *ei = d.ev_idx + (int64_t)slot * d.ev_idx_stride;
+        const int32_t *ei = ev_idx + (int64_t)slot * st.ev_idx;
         ev0 = ei[it.clique];
         ev1 = ei[it.clique + 1];
         for (int e = ev0; e < ev1; ++e) {
@@ -99,112 +117,124 @@ __device__ __forceinline__ void pass_body(const JtDev &d, const JtItem &it, cons
         }
     }
 
-    const float scale = it.scale_clique >= 0 ? d.scale[(int64_t)slot * d.scale_stride + it.scale_clique] : 1.0f;
-    const float *__restrict__ src =
-        (it.src_kind == JT_SRC_INIT ? d.init
-                                    : (it.src_kind == JT_SRC_COLL ? d.coll + (int64_t)slot * d.coll_stride
-                                                                  : d.out + (int64_t)slot * d.out_stride)) +
+    const float scale = it.scale_clique >= 0 ? scale_arr[(int64_t)slot * st.scale + it.scale_clique] : 1.0f;
+    const float *src =
+        (it.src_kind == JT_SRC_INIT ? init
+                                    : (it.src_kind == JT_SRC_COLL ? coll + (int64_t)slot * st.coll
+                                                                  : out + (int64_t)slot * st.out)) +
         it.src_off;
-    float *__restrict__ dst = nullptr;
-    if (it.dst_kind == JT_DST_COLL) dst = d.coll + (int64_t)slot * d.coll_stride + it.dst_off;
-    if (it.dst_kind == JT_DST_OUT) dst = d.out + (int64_t)slot * d.out_stride + it.dst_off;
+    float *dst = nullptr;
+    if (it.dst_kind == JT_DST_COLL) dst = coll + (int64_t)slot * st.coll + it.dst_off;
+    if (it.dst_kind == JT_DST_OUT) dst = out + (int64_t)slot * st.out + it.dst_off;
 
     const bool has_out = it.out_view >= 0;
-    JtView OV;
-    if (has_out) OV = d.views[it.out_view];
-    float *__restrict__ part = d.partial + (int64_t)slot * d.partial_stride + it.partial_off;
+    const int32_t rout_off = it.o_rout_tile;
+    float *part = partial + (int64_t)slot * st.partial + it.partial_off;
 
+    // issue the loads of up to JT_UNROLL tiles [t0, min(t0 + U, t1))
+    auto issue = [&](TileBatch<VEC> &B, int t0, int t1, int tile_k) {
+#pragma unroll
+        for (int u = 0; u < JT_UNROLL; ++u) {
+            const int t = t0 + u;
+            B.o[u] = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) B.x[u][q] = 0.f;
+            if (t < t1) {
+                const int o = has_out ? tile_k + meta[rout_off + t] : t;
+                B.o[u] = o;
+                bool zero = false;
+                for (int e = ev0; e < ev1; ++e) {
+                    const JtEv E = evs[e];
+                    if (E.outer && ((o / E.stride) % E.card) != E.digit) zero = true;
+                }
+                if (!zero) {
+                    const float *base = src + (int64_t)o * T;
+                    if (VEC == 4) {
+                        if (valid[0]) {
+                            const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
+                            B.x[u][0] = v4.x;
+                            B.x[u][1] = v4.y;
+                            B.x[u][2] = v4.z;
+                            B.x[u][3] = v4.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (valid[q]) B.x[u][q] = base[pos[q]];
+                    }
+                }
+            }
+        }
+    };
+    // multiply in the gathers, mask, scale, store, accumulate
+    auto consume = [&](const TileBatch<VEC> &B, int t0, int t1, float (&acc)[4]) {
+#pragma unroll
+        for (int u = 0; u < JT_UNROLL; ++u) {
+            if (t0 + u >= t1) break;
+            const int o = B.o[u];
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = B.x[u][q];
+#pragma unroll
+            for (int gg = 0; gg < JT_NG_REG; ++gg) {
+                if (gg < ngr) {
+                    const int jo = meta[gr[gg].jout_off + o];
+                    if (gr[gg].in_lds) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] *= lds_ratio[gr[gg].off + jo + jin[gg][q]];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] *= sep_slot[gr[gg].off + jo + jin[gg][q]];
+                    }
+                }
+            }
+            for (int gg = JT_NG_REG; gg < ng; ++gg) {
+                const JtGather G = gathers[it.gather_base + gg];
+                const int jo = meta[G.jout_off + o];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = jo + (valid[q] ? meta[G.jin_off + pos[q]] : 0);
+                    v[q] *= G.lds_off >= 0 ? lds_ratio[G.lds_off + j] : sep_slot[G.sep_off + j];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = keep[q] ? v[q] * scale : 0.f;
+            if (dst) {
+                float *b = dst + (int64_t)o * T;
+                if (VEC == 4) {
+                    if (valid[0]) *reinterpret_cast<float4 *>(b + pos[0]) = make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (valid[q]) b[pos[q]] = v[q];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += v[q];
+        }
+    };
+
+    TileBatch<VEC> A, B;
     for (int g = task.g0 + wave; g < task.g1; g += JT_WAVES_PER_BLOCK) {
         int k = 0, sp = 0, q0, q1, tile_k = 0;
         if (has_out) {
             k = g / it.nsplit;
             sp = g - k * it.nsplit;
             q0 = sp * it.tpg;
-            q1 = min(q0 + it.tpg, OV.n_rout);
-            tile_k = meta[OV.kout_tile_off + k];
+            q1 = min(q0 + it.tpg, it.o_n_rout);
+            tile_k = meta[it.o_kout_tile + k];
         } else {
             q0 = g * it.tpg;
             q1 = min(q0 + it.tpg, it.n_tiles);
         }
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int qq = q0; qq < q1; qq += JT_UNROLL) {
-            int o[JT_UNROLL];
-            float x[JT_UNROLL][4];
-#pragma unroll
-            for (int u = 0; u < JT_UNROLL; ++u) {
-                const int t = qq + u;
-                o[u] = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) x[u][q] = 0.f;
-                if (t < q1) {
-                    o[u] = has_out ? tile_k + meta[OV.rout_tile_off + t] : t;
-                    bool zero = false;
-                    for (int e = ev0; e < ev1; ++e) {
-                        const JtEv E = evs[e];
-                        if (E.outer && ((o[u] / E.stride) % E.card) != E.digit) zero = true;
-                    }
-                    if (!zero) {
-                        const float *base = src + (int64_t)o[u] * T;
-                        if (VEC == 4) {
-                            if (valid[0]) {
-                                const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
-                                x[u][0] = v4.x;
-                                x[u][1] = v4.y;
-                                x[u][2] = v4.z;
-                                x[u][3] = v4.w;
-                            }
-                        } else {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                if (valid[q]) x[u][q] = base[pos[q]];
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < JT_UNROLL; ++u) {
-                if (qq + u >= q1) break;
-                float v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = x[u][q];
-#pragma unroll
-                for (int gg = 0; gg < JT_NG_REG; ++gg) {
-                    if (gg < ngr) {
-                        const int jo = meta[gr[gg].jout_off + o[u]];
-                        if (gr[gg].in_lds) {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) v[q] *= lds_ratio[gr[gg].off + jo + jin[gg][q]];
-                        } else {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) v[q] *= sep_slot[gr[gg].off + jo + jin[gg][q]];
-                        }
-                    }
-                }
-                for (int gg = JT_NG_REG; gg < ng; ++gg) {
-                    const JtGather G = d.gathers[it.gather_base + gg];
-                    const JtView V = d.views[G.view];
-                    const int jo = meta[V.jout_off + o[u]];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = jo + (valid[q] ? meta[V.jin_off + pos[q]] : 0);
-                        v[q] *= G.lds_off >= 0 ? lds_ratio[G.lds_off + j] : sep_slot[G.sep_off + j];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = keep[q] ? v[q] * scale : 0.f;
-                if (dst) {
-                    float *b = dst + (int64_t)o[u] * T;
-                    if (VEC == 4) {
-                        if (valid[0]) *reinterpret_cast<float4 *>(b + pos[0]) = make_float4(v[0], v[1], v[2], v[3]);
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if (valid[q]) b[pos[q]] = v[q];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] += v[q];
-            }
+        // two batches of tiles in flight: load one while the other is consumed
+        issue(A, q0, q1, tile_k);
+        for (int qq = q0; qq < q1; qq += 2 * JT_UNROLL) {
+            if (qq + JT_UNROLL < q1) issue(B, qq + JT_UNROLL, q1, tile_k);
+            consume(A, qq, q1, acc);
+            if (qq + 2 * JT_UNROLL < q1) issue(A, qq + 2 * JT_UNROLL, q1, tile_k);
+            if (qq + JT_UNROLL < q1) consume(B, qq + JT_UNROLL, q1, acc);
         }
         if (!has_out) continue;
 
@@ -214,11 +244,11 @@ __device__ __forceinline__ void pass_body(const JtDev &d, const JtItem &it, cons
         for (int q = 0; q < 4; ++q)
             if (valid[q]) lds_red[pos[q]] = acc[q];
         wave_sync();
-        const int n_cls = OV.n_cls, m_in = OV.m_in;
-        const int jk = meta[OV.kout_j_off + k];
-        float *pout = part + (int64_t)sp * OV.ssize + jk;
-        const int32_t *perm = meta + OV.perm_off;
-        const int32_t *clsj = meta + OV.clsj_off;
+        const int n_cls = it.o_n_cls, m_in = it.o_m_in;
+        const int jk = meta[it.o_kout_j + k];
+        float *pout = part + (int64_t)sp * it.o_ssize + jk;
+        const int32_t *perm = meta + it.o_perm;
+        const int32_t *clsj = meta + it.o_clsj;
         if (n_cls >= JT_WAVE) {
             for (int cls = lane; cls < n_cls; cls += JT_WAVE) {
                 float s = 0.f;
@@ -241,76 +271,112 @@ __device__ __forceinline__ void pass_body(const JtDev &d, const JtItem &it, cons
 }  // namespace
 
 // One launch = the passes of one tree level (or one message) for every slot.
-extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(JtDev d, int task_begin, int n_tasks) {
+// Buffers are separate __restrict__ parameters so the compiler can prove the
+// metadata is never written by the kernel and read it through the scalar
+// unit (uniform loads that do not wait on the streaming vector loads).
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
+    const JtTask *__restrict__ tasks, const JtItem *__restrict__ items, const JtGather *__restrict__ gathers,
+    const int32_t *__restrict__ meta, const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
+    const float *__restrict__ init, float *__restrict__ coll, float *__restrict__ out,
+    const float *__restrict__ sep, const float *__restrict__ scale, float *__restrict__ partial, PassStrides st,
+    int task_begin, int n_tasks) {
     __shared__ float lds_ratio[JT_LDS_RATIO_FLOATS];
     __shared__ float lds_red[JT_WAVES_PER_BLOCK][JT_TILE_MAX];
     const int slot = blockIdx.x / n_tasks;
-    const JtTask task = d.tasks[task_begin + (blockIdx.x - slot * n_tasks)];
-    const JtItem it = d.items[task.item];
+    const JtTask task = tasks[task_begin + (blockIdx.x - slot * n_tasks)];
+    const JtItem it = items[task.item];
     // stage the ratio tables this pass multiplies in
-    const float *sep_slot = d.sep + (int64_t)slot * d.sep_stride;
+    const float *sep_slot = sep + (int64_t)slot * st.sep;
     for (int g = 0; g < it.n_gather_lds; ++g) {
-        const JtGather G = d.gathers[it.gather_base + g];
+        const JtGather G = gathers[it.gather_base + g];
         for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = sep_slot[G.sep_off + j];
     }
     __syncthreads();
     float *red = lds_red[threadIdx.x / JT_WAVE];
     if (it.vec == 4)
-        pass_body<4>(d, it, task, slot, lds_ratio, red);
+        pass_body<4>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st, lds_ratio,
+                     red);
     else
-        pass_body<1>(d, it, task, slot, lds_ratio, red);
+        pass_body<1>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st, lds_ratio,
+                     red);
 }
 
-// One block per (message, slot).
-extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev d, int msg_begin, int n_msgs) {
+// Finalize: each block sums the split partials of jc separator entries
+// (JT_BLOCK / jc split rows per column, fixed order), writes them, and adds a
+// block sum to the message's scratch.  The block that arrives last forms
+// sigma from the block sums in block order, updates the log-scales, and
+// rescales the whole separator table (and forms new/old, 0/0 := 0).
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev d, int ftask_begin, int n_ftasks) {
     __shared__ float red[JT_BLOCK];
     __shared__ double dred[JT_BLOCK];
     __shared__ float sh_f;
+    __shared__ int sh_last;
     const int tid = threadIdx.x;
-    const int slot = blockIdx.x / n_msgs;
-    const JtMsg m = d.msgs[msg_begin + (blockIdx.x - slot * n_msgs)];
+    const int slot = blockIdx.x / n_ftasks;
+    const JtFTask ft = d.ftasks[ftask_begin + (blockIdx.x - slot * n_ftasks)];
+    const JtMsg m = d.msgs[ft.msg];
     const int nc = d.n_cliques;
     const float *P = d.partial + (int64_t)slot * d.partial_stride + m.partial_off;
     float *sep = d.sep + (int64_t)slot * d.sep_stride;
     double *lam = d.lam + (int64_t)slot * d.lam_stride;
     float *scl = d.scale + (int64_t)slot * d.scale_stride;
+    double *fsig = d.fsig + (int64_t)slot * d.fsig_stride;
+    int32_t *fcnt = d.fcnt + (int64_t)slot * d.fcnt_stride;
     const int ssize = m.ssize, nsplit = m.nsplit;
     float *raw = nullptr;
     if (m.kind == JT_MSG_COLLECT) raw = sep + m.sepc_off;
     if (m.kind == JT_MSG_DIST || m.kind == JT_MSG_PLAIN) raw = sep + m.sepd_off;
 
-    // sum the split partials: column j, rows split over R thread groups
-    int sp2 = 1;
-    while (sp2 < ssize && sp2 < JT_BLOCK) sp2 <<= 1;
-    const int R = JT_BLOCK / sp2;
-    const int jj = tid % sp2, r = tid / sp2;
-    double local = 0.0;
-    for (int j0 = 0; j0 < ssize; j0 += sp2) {
-        const int j = j0 + jj;
-        float s = 0.f;
-        if (j < ssize)
-            for (int p = r; p < nsplit; p += R) s += P[(int64_t)p * ssize + j];
-        red[tid] = s;
-        __syncthreads();
-        for (int h = R >> 1; h > 0; h >>= 1) {
-            if (r < h) red[tid] += red[tid + h * sp2];
-            __syncthreads();
+    const int jc = ft.jc, R = JT_BLOCK / jc;
+    const int jj = tid & (jc - 1), r = tid / jc;
+    const int j = ft.j0 + jj;
+    float s = 0.f;
+    if (j < ft.j1) {
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        int p = r;
+        for (; p + 3 * R < nsplit; p += 4 * R) {
+            a0 += P[(int64_t)p * ssize + j];
+            a1 += P[(int64_t)(p + R) * ssize + j];
+            a2 += P[(int64_t)(p + 2 * R) * ssize + j];
+            a3 += P[(int64_t)(p + 3 * R) * ssize + j];
         }
-        if (r == 0 && j < ssize) {
-            const float v = red[jj];
-            if (raw) raw[j] = v;
-            local += (double)v;
-        }
+        for (; p < nsplit; p += R) a0 += P[(int64_t)p * ssize + j];
+        s = (a0 + a1) + (a2 + a3);
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int h = R >> 1; h > 0; h >>= 1) {
+        if (r < h) red[tid] += red[tid + h * jc];
         __syncthreads();
     }
-    dred[tid] = local;
+    double v = 0.0;
+    if (r == 0 && j < ft.j1) {
+        const float x = red[jj];
+        if (raw) raw[j] = x;
+        v = (double)x;
+    }
+    dred[tid] = v;
     __syncthreads();
     for (int h = JT_BLOCK >> 1; h > 0; h >>= 1) {
         if (tid < h) dred[tid] += dred[tid + h];
         __syncthreads();
     }
+    if (ft.nb > 1) {
+        if (tid == 0) fsig[m.fbase + ft.b] = dred[0];
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) sh_last = (atomicAdd(&fcnt[ft.msg], 1) == ft.nb - 1);
+        __syncthreads();
+        if (!sh_last) return;
+        __threadfence();
+    }
     if (tid == 0) {
-        const double sigma = dred[0];
+        double sigma = dred[0];
+        if (ft.nb > 1) {
+            sigma = 0.0;
+            for (int b = 0; b < ft.nb; ++b) sigma += fsig[m.fbase + b];
+            fcnt[ft.msg] = 0;    // ready for the next propagation
+        }
         const double ns = (double)ssize;
         double f = 0.0;
         switch (m.kind) {
@@ -378,21 +444,21 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev 
     __syncthreads();
     const float f = sh_f;
     if (m.kind == JT_MSG_COLLECT) {
-        for (int j = tid; j < ssize; j += JT_BLOCK) raw[j] = raw[j] * f;
+        for (int jx = tid; jx < ssize; jx += JT_BLOCK) raw[jx] = raw[jx] * f;
     } else if (m.kind == JT_MSG_DIST) {
         const float *oldc = sep + m.sepc_off;
-        for (int j = tid; j < ssize; j += JT_BLOCK) {
-            const float nw = raw[j] * f;
-            const float od = oldc[j];
-            raw[j] = (od == 0.f) ? 0.f : nw / od;
+        for (int jx = tid; jx < ssize; jx += JT_BLOCK) {
+            const float nw = raw[jx] * f;
+            const float od = oldc[jx];
+            raw[jx] = (od == 0.f) ? 0.f : nw / od;
         }
     } else if (m.kind == JT_MSG_PLAIN) {
         float *oldc = sep + m.sepc_off;
-        for (int j = tid; j < ssize; j += JT_BLOCK) {
-            const float nw = raw[j] * f;
-            const float od = oldc[j];
-            raw[j] = (od == 0.f) ? 0.f : nw / od;
-            oldc[j] = nw;
+        for (int jx = tid; jx < ssize; jx += JT_BLOCK) {
+            const float nw = raw[jx] * f;
+            const float od = oldc[jx];
+            raw[jx] = (od == 0.f) ? 0.f : nw / od;
+            oldc[jx] = nw;
         }
     }
 }
@@ -410,14 +476,23 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_plain_init_kernel(JtDe
 // host-side launchers (the C ABI lives in jt_api.cpp)
 
 hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, hipStream_t s) {
-    hipLaunchKernelGGL(jt_pass_kernel, dim3((unsigned)n_tasks * (unsigned)n_slots), dim3(JT_BLOCK), 0, s, d,
-                       task_begin, n_tasks);
+    PassStrides st;
+    st.coll = d.coll_stride;
+    st.out = d.out_stride;
+    st.sep = d.sep_stride;
+    st.partial = d.partial_stride;
+    st.scale = d.scale_stride;
+    st.ev_idx = d.ev_idx_stride;
+    st.ev_ent = d.ev_ent_stride;
+    hipLaunchKernelGGL(jt_pass_kernel, dim3((unsigned)n_tasks * (unsigned)n_slots), dim3(JT_BLOCK), 0, s, d.tasks,
+                       d.items, d.gathers, d.meta, d.ev_idx, d.ev_ent, d.init, d.coll, d.out, d.sep, d.scale,
+                       d.partial, st, task_begin, n_tasks);
     return hipGetLastError();
 }
 
-hipError_t jt_launch_finalize(const JtDev &d, int msg_begin, int n_msgs, int n_slots, hipStream_t s) {
-    hipLaunchKernelGGL(jt_finalize_kernel, dim3((unsigned)n_msgs * (unsigned)n_slots), dim3(JT_BLOCK), 0, s, d,
-                       msg_begin, n_msgs);
+hipError_t jt_launch_finalize(const JtDev &d, int ftask_begin, int n_ftasks, int n_slots, hipStream_t s) {
+    hipLaunchKernelGGL(jt_finalize_kernel, dim3((unsigned)n_ftasks * (unsigned)n_slots), dim3(JT_BLOCK), 0, s, d,
+                       ftask_begin, n_ftasks);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ namespace jt {
 namespace {
 
 constexpr int64_t kAlignFloats = 64;       // 256-byte alignment of every table
-constexpr int64_t kGroupEntries = 2048;    // target entries per wave group
+constexpr int64_t kTargetBlocks = 1024;    // blocks per launch the grouping aims for
 constexpr int64_t kPartialMax = 65536;     // cap on split partial floats per message
 constexpr int64_t kMaxMeta = int64_t(1) << 30;
 
@@ -183,9 +183,38 @@ struct GatherSpec {
 };
 
 // Append one pass item and the tasks that cover it.
+// Group size of a launch that streams `level_entries` table entries per
+// slot: small levels are cut finer (to spread over the chip), large ones
+// coarser (to amortize each wave's set-up and its in-tile reduction).  It
+// depends on one slot's work only, so a query's summation order -- and hence
+// its bits -- do not depend on how many other queries share the launch.
+int64_t group_entries_for(int64_t level_entries) {
+    return std::min<int64_t>(8192, std::max<int64_t>(1024, level_entries / 2048));
+}
+
+// Blocks over the items [i0, i1) of one launch: each block takes `gpb`
+// consecutive groups of one item, about kTargetBlocks blocks per launch.
+void emit_tasks(Plan &P, int32_t i0, int32_t i1) {
+    int64_t groups = 0;
+    for (int32_t i = i0; i < i1; ++i) groups += P.items[i].n_groups;
+    groups *= P.n_slots;
+    const int64_t per = (groups + kTargetBlocks - 1) / kTargetBlocks;
+    const int32_t gpb = (int32_t)std::max<int64_t>(
+        JT_WAVES_PER_BLOCK, (per + JT_WAVES_PER_BLOCK - 1) / JT_WAVES_PER_BLOCK * JT_WAVES_PER_BLOCK);
+    for (int32_t i = i0; i < i1; ++i)
+        for (int32_t g0 = 0; g0 < P.items[i].n_groups; g0 += gpb) {
+            JtTask t;
+            t.item = i;
+            t.g0 = g0;
+            t.g1 = std::min<int32_t>(P.items[i].n_groups, g0 + gpb);
+            t.pad = 0;
+            P.tasks.push_back(t);
+        }
+}
+
 int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t dst_kind,
                  int64_t dst_off, const std::vector<GatherSpec> &gs, int32_t scale_clique,
-                 int32_t out_view, int64_t partial_off, int64_t &bytes_acc) {
+                 int32_t out_view, int64_t partial_off, int64_t &bytes_acc, int64_t group_entries) {
     const CliqueInfo &C = P.cl[c];
     JtItem it;
     std::memset(&it, 0, sizeof(it));
@@ -207,6 +236,8 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         G.view = (c == g.edge) ? E.view_child : E.view_parent;
         G.sep_off = g.dist ? E.sepd_off : E.sepc_off;
         G.ssize = (int32_t)E.ssize;
+        G.jin_off = (int32_t)P.views[G.view].jin_off;
+        G.jout_off = (int32_t)P.views[G.view].jout_off;
         if (lds_open && lds + E.ssize <= JT_LDS_RATIO_FLOATS) {
             G.lds_off = lds;
             lds += (int32_t)E.ssize;
@@ -223,12 +254,24 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
     it.ev = (src_kind == JT_SRC_INIT) ? 1 : 0;
     it.out_view = out_view;
     it.partial_off = partial_off;
-    const int64_t tiles_per_group = std::max<int64_t>(1, kGroupEntries / C.T);
+    const int64_t tiles_per_group = std::max<int64_t>(1, group_entries / C.T);
     if (out_view >= 0) {
         const JtView &V = P.views[out_view];
+        it.o_kout_tile = (int32_t)V.kout_tile_off;
+        it.o_kout_j = (int32_t)V.kout_j_off;
+        it.o_rout_tile = (int32_t)V.rout_tile_off;
+        it.o_perm = (int32_t)V.perm_off;
+        it.o_clsj = (int32_t)V.clsj_off;
+        it.o_n_rout = V.n_rout;
+        it.o_n_cls = V.n_cls;
+        it.o_m_in = V.m_in;
+        it.o_ssize = V.ssize;
+        // split partials (nsplit x |phi_S| floats) stay below 1/32 of the
+        // table, or one separator table when that is larger
+        const int64_t cap = std::max<int64_t>(V.ssize, std::min<int64_t>(kPartialMax, C.size / 32));
         int64_t tpg = std::min<int64_t>(V.n_rout, tiles_per_group);
         int64_t nsplit = (V.n_rout + tpg - 1) / tpg;
-        while (nsplit * V.ssize > kPartialMax && tpg < V.n_rout) {
+        while (nsplit * V.ssize > cap && tpg < V.n_rout) {
             tpg *= 2;
             nsplit = (V.n_rout + tpg - 1) / tpg;
         }
@@ -243,15 +286,6 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
     }
     P.items.push_back(it);
     const int32_t idx = (int32_t)P.items.size() - 1;
-    // one group per wave, JT_WAVES_PER_BLOCK groups per block
-    for (int32_t g0 = 0; g0 < it.n_groups; g0 += JT_WAVES_PER_BLOCK) {
-        JtTask t;
-        t.item = idx;
-        t.g0 = g0;
-        t.g1 = std::min<int32_t>(it.n_groups, g0 + JT_WAVES_PER_BLOCK);
-        t.pad = 0;
-        P.tasks.push_back(t);
-    }
     // FP32 table bytes: shared initial tables are read once for all slots
     const int64_t tb = 4 * C.size;
     bytes_acc += (src_kind == JT_SRC_INIT) ? tb : tb * P.n_slots;
@@ -261,6 +295,33 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
 
 int32_t item_nsplit(const Plan &P, int32_t item) { return P.items[item].nsplit; }
 
+
+// Cut the finalize of message `mi` into blocks: jc separator entries per
+// block (a power of two), JT_BLOCK / jc split rows, at most ~8 rows per thread.
+void add_ftasks(Plan &P, int32_t mi, int64_t &fsig_count) {
+    JtMsg &m = P.msgs[mi];
+    int32_t rows = 1;
+    while (rows < JT_BLOCK && (int64_t)rows * 8 < m.nsplit) rows <<= 1;
+    int32_t jc = JT_BLOCK / rows;
+    int32_t sp2 = 1;
+    while (sp2 < m.ssize && sp2 < JT_BLOCK) sp2 <<= 1;
+    if (sp2 < jc) jc = sp2;
+    const int32_t nb = (m.ssize + jc - 1) / jc;
+    m.fbase = (int32_t)fsig_count;
+    m.nfb = nb;
+    fsig_count += nb;
+    for (int32_t b = 0; b < nb; ++b) {
+        JtFTask f;
+        std::memset(&f, 0, sizeof(f));
+        f.msg = mi;
+        f.j0 = b * jc;
+        f.j1 = std::min<int32_t>(m.ssize, (b + 1) * jc);
+        f.jc = jc;
+        f.b = b;
+        f.nb = nb;
+        P.ftasks.push_back(f);
+    }
+}
 
 // Check, on the host, that every index the kernels derive from the plan
 // stays inside its buffer.  Run once per compiled tree; a failure here is a
@@ -320,6 +381,8 @@ bool verify_plan(const Plan &P, std::string &why) {
             const JtGather &G = P.gathers[it.gather_base + g];
             if (G.view < 0 || G.view >= (int32_t)P.views.size() || P.views[G.view].clique != it.clique) return bad("gather view");
             if (P.views[G.view].ssize != G.ssize) return bad("gather size");
+            if (G.jin_off != P.views[G.view].jin_off || G.jout_off != P.views[G.view].jout_off)
+                return bad("gather tables");
             if (G.sep_off < 0 || G.sep_off + (int64_t)G.ssize > P.sep_stride) return bad("gather separator range");
             if ((g < it.n_gather_lds) != (G.lds_off >= 0)) return bad("gather LDS order");
             if (G.lds_off >= 0 && G.lds_off + G.ssize > it.lds_floats) return bad("gather LDS range");
@@ -330,6 +393,10 @@ bool verify_plan(const Plan &P, std::string &why) {
             if (it.out_view >= (int32_t)P.views.size()) return bad("output view");
             const JtView &V = P.views[it.out_view];
             if (V.clique != it.clique) return bad("output view clique");
+            if (it.o_kout_tile != V.kout_tile_off || it.o_kout_j != V.kout_j_off || it.o_rout_tile != V.rout_tile_off ||
+                it.o_perm != V.perm_off || it.o_clsj != V.clsj_off || it.o_n_rout != V.n_rout ||
+                it.o_n_cls != V.n_cls || it.o_m_in != V.m_in || it.o_ssize != V.ssize)
+                return bad("output view copy");
             if ((int64_t)it.tpg * it.nsplit < V.n_rout || (int64_t)it.tpg * (it.nsplit - 1) >= V.n_rout)
                 return bad("split cover");
             if ((int64_t)it.n_groups != (int64_t)V.n_kout * it.nsplit) return bad("group count");
@@ -357,10 +424,19 @@ bool verify_plan(const Plan &P, std::string &why) {
         }
         if (m.child_base < 0 || m.child_base + m.n_children > (int32_t)P.child_edges.size()) return bad("children range");
     }
+    for (const JtFTask &f : P.ftasks) {
+        if (f.msg < 0 || f.msg >= (int32_t)P.msgs.size()) return bad("finalize message");
+        const JtMsg &m = P.msgs[f.msg];
+        if (f.jc < 1 || f.jc > JT_BLOCK || (f.jc & (f.jc - 1))) return bad("finalize columns");
+        if (f.j0 < 0 || f.j0 >= f.j1 || f.j1 > m.ssize || f.j1 - f.j0 > f.jc) return bad("finalize range");
+        if (f.nb != m.nfb || f.b < 0 || f.b >= f.nb) return bad("finalize block");
+        if (m.fbase < 0 || m.fbase + m.nfb > P.fsig_stride) return bad("finalize scratch");
+    }
+    if ((int64_t)P.msgs.size() > P.fcnt_stride) return bad("finalize counters");
     for (const std::vector<Launch> *L : {&P.fused, &P.plain})
         for (const Launch &l : *L) {
             if (l.is_pass == 1 && (l.begin < 0 || l.begin + l.count > (int32_t)P.tasks.size())) return bad("launch tasks");
-            if (l.is_pass == 0 && (l.begin < 0 || l.begin + l.count > (int32_t)P.msgs.size())) return bad("launch msgs");
+            if (l.is_pass == 0 && (l.begin < 0 || l.begin + l.count > (int32_t)P.ftasks.size())) return bad("launch ftasks");
         }
     for (int32_t c = 0; c < P.n_cliques; ++c)
         for (const VDigit &d : P.cl[c].digits)
@@ -529,8 +605,12 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         by_depth[P.cl[c].depth].push_back(c);
     }
     int64_t bytes = 0;
+    int64_t fsig_count = 0;
     for (int32_t h = 0; h <= P.height; ++h) {
-        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size();
+        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
+        int64_t level_entries = 0;
+        for (int32_t c : by_height[h]) level_entries += P.cl[c].size;
+        const int64_t ge = group_entries_for(level_entries);
         std::vector<JtMsg> level_msgs;
         for (int32_t c : by_height[h]) {
             const CliqueInfo &C = P.cl[c];
@@ -541,7 +621,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             // partial size is known once the item's split is chosen: add the
             // item first with a placeholder, then patch its offset.
             const int32_t it = add_item(P, c, JT_SRC_INIT, C.init_off, C.children.empty() ? JT_DST_NONE : JT_DST_COLL,
-                                        C.coll_off, gs, -1, view, 0, bytes);
+                                        C.coll_off, gs, -1, view, 0, bytes, ge);
             const int64_t ss = P.views[view].ssize;
             const int64_t poff = add_partial(ss * item_nsplit(P, it));
             P.items[it].partial_off = poff;
@@ -561,12 +641,19 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             m.sepd_off = is_root ? 0 : P.edge[c].sepd_off;
             level_msgs.push_back(m);
         }
+        emit_tasks(P, i0, (int32_t)P.items.size());
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
+        const int32_t f0 = (int32_t)P.ftasks.size();
+        for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
         P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        P.fused.push_back({0, m0, (int32_t)P.msgs.size() - m0});
+        P.fused.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
     }
     for (int32_t d = 0; d <= P.depth; ++d) {
-        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size();
+        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
+        int64_t level_entries = 0;
+        for (int32_t c : by_depth[d])
+            level_entries += P.cl[c].size * std::max<int64_t>(1, (int64_t)P.cl[c].children.size());
+        const int64_t ge = group_entries_for(level_entries);
         std::vector<JtMsg> level_msgs;
         for (int32_t c : by_depth[d]) {
             const CliqueInfo &C = P.cl[c];
@@ -576,14 +663,14 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             const int32_t src_kind = leaf ? JT_SRC_INIT : JT_SRC_COLL;
             const int64_t src_off = leaf ? C.init_off : C.coll_off;
             if (leaf) {
-                add_item(P, c, src_kind, src_off, JT_DST_OUT, C.out_off, gs, c, -1, 0, bytes);
+                add_item(P, c, src_kind, src_off, JT_DST_OUT, C.out_off, gs, c, -1, 0, bytes, ge);
                 continue;
             }
             for (size_t k = 0; k < C.children.size(); ++k) {
                 const int32_t ch = C.children[k];
                 const int32_t view = P.edge[ch].view_parent;
                 const int32_t it = add_item(P, c, src_kind, src_off, k == 0 ? JT_DST_OUT : JT_DST_NONE,
-                                            C.out_off, gs, c, view, 0, bytes);
+                                            C.out_off, gs, c, view, 0, bytes, ge);
                 const int64_t ss = P.views[view].ssize;
                 const int64_t poff = add_partial(ss * item_nsplit(P, it));
                 P.items[it].partial_off = poff;
@@ -601,9 +688,12 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                 level_msgs.push_back(m);
             }
         }
+        emit_tasks(P, i0, (int32_t)P.items.size());
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
+        const int32_t f0 = (int32_t)P.ftasks.size();
+        for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
         P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        if (!level_msgs.empty()) P.fused.push_back({0, m0, (int32_t)P.msgs.size() - m0});
+        if (!level_msgs.empty()) P.fused.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
     }
     P.bytes_fused = bytes;
 
@@ -612,8 +702,11 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     bytes = 0;
     {
         const int32_t t0 = (int32_t)P.tasks.size();
+        const int32_t i0 = (int32_t)P.items.size();
+        const int64_t ge = group_entries_for(P.total_entries);
         for (int32_t c = 0; c < nc; ++c)
-            add_item(P, c, JT_SRC_INIT, P.cl[c].init_off, JT_DST_OUT, P.cl[c].out_off, {}, -1, -1, 0, bytes);
+            add_item(P, c, JT_SRC_INIT, P.cl[c].init_off, JT_DST_OUT, P.cl[c].out_off, {}, -1, -1, 0, bytes, ge);
+        emit_tasks(P, i0, (int32_t)P.items.size());
         P.plain_reset_task_begin = t0;
         P.plain_reset_task_count = (int32_t)P.tasks.size() - t0;
         P.plain.push_back({2, 0, 0});   // separators := 1, log-scales := 0
@@ -623,7 +716,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         const int32_t view_from = (from == e) ? P.edge[e].view_child : P.edge[e].view_parent;
         const int32_t t0 = (int32_t)P.tasks.size();
         const int32_t it = add_item(P, from, JT_SRC_OUT, P.cl[from].out_off, JT_DST_NONE, 0, {}, -1,
-                                    view_from, 0, bytes);
+                                    view_from, 0, bytes, group_entries_for(P.cl[from].size));
+        emit_tasks(P, it, it + 1);
         const int64_t ss = P.edge[e].ssize;
         const int64_t poff = add_partial(ss * item_nsplit(P, it));
         P.items[it].partial_off = poff;
@@ -640,10 +734,13 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         m.sepc_off = P.edge[e].sepc_off;
         m.sepd_off = P.edge[e].sepd_off;
         P.msgs.push_back(m);
-        P.plain.push_back({0, (int32_t)P.msgs.size() - 1, 1});
+        const int32_t f0 = (int32_t)P.ftasks.size();
+        add_ftasks(P, (int32_t)P.msgs.size() - 1, fsig_count);
+        P.plain.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         const int32_t t1 = (int32_t)P.tasks.size();
-        add_item(P, to, JT_SRC_OUT, P.cl[to].out_off, JT_DST_OUT, P.cl[to].out_off, {{e, true}}, -1, -1, 0,
-                 bytes);
+        const int32_t it2 = add_item(P, to, JT_SRC_OUT, P.cl[to].out_off, JT_DST_OUT, P.cl[to].out_off, {{e, true}},
+                                     -1, -1, 0, bytes, group_entries_for(P.cl[to].size));
+        emit_tasks(P, it2, it2 + 1);
         P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
     };
     // Algorithm 2 (post-order) and Algorithm 3 (pre-order), children ascending
@@ -678,9 +775,11 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         // read-out: totals of every calibrated table, then normalize in place
         const int32_t t0 = (int32_t)P.tasks.size();
         const int32_t m0 = (int32_t)P.msgs.size();
+        const int32_t i0 = (int32_t)P.items.size();
+        const int64_t ge = group_entries_for(P.total_entries);
         for (int32_t c = 0; c < nc; ++c) {
             const int32_t view = P.cl[c].total_view;
-            const int32_t it = add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_NONE, 0, {}, -1, view, 0, bytes);
+            const int32_t it = add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_NONE, 0, {}, -1, view, 0, bytes, ge);
             const int64_t poff = add_partial(item_nsplit(P, it));
             P.items[it].partial_off = poff;
             JtMsg m;
@@ -694,11 +793,16 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             m.partial_off = poff;
             P.msgs.push_back(m);
         }
+        const int32_t f0 = (int32_t)P.ftasks.size();
+        for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
+        emit_tasks(P, i0, (int32_t)P.items.size());
         P.plain.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        P.plain.push_back({0, m0, (int32_t)P.msgs.size() - m0});
+        P.plain.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         const int32_t t1 = (int32_t)P.tasks.size();
+        const int32_t i1 = (int32_t)P.items.size();
         for (int32_t c = 0; c < nc; ++c)
-            add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_OUT, P.cl[c].out_off, {}, c, -1, 0, bytes);
+            add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_OUT, P.cl[c].out_off, {}, c, -1, 0, bytes, ge);
+        emit_tasks(P, i1, (int32_t)P.items.size());
         P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
     }
     P.bytes_plain = bytes;
@@ -706,6 +810,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         return fail(err, JT_E_TOO_LARGE, "partial region too large");
 
     // ---------------- workspace layout ----------------
+    P.fsig_stride = align_up(std::max<int64_t>(1, fsig_count), 32);
+    P.fcnt_stride = align_up(std::max<int64_t>(1, (int64_t)P.msgs.size()), kAlignFloats);
     P.lam_stride = align_up(3 * (int64_t)nc + 1, 32);
     P.scale_stride = align_up(nc, kAlignFloats);
     P.ev_idx_stride = align_up((int64_t)nc + 1, kAlignFloats);
@@ -724,6 +830,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_tasks = region(P.tasks.size() * sizeof(JtTask));
     P.off_msgs = region(P.msgs.size() * sizeof(JtMsg));
     P.off_child = region(std::max<size_t>(1, P.child_edges.size()) * sizeof(int32_t));
+    P.off_ftasks = region(std::max<size_t>(1, P.ftasks.size()) * sizeof(JtFTask));
     P.off_init = region((size_t)P.init_floats * sizeof(float));
     P.off_coll = region(S * (size_t)P.coll_stride * sizeof(float));
     P.off_out = region(S * (size_t)P.out_stride * sizeof(float));
@@ -734,6 +841,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_flag = region(S * sizeof(int32_t));
     P.off_ev_idx = region(S * (size_t)P.ev_idx_stride * sizeof(int32_t));
     P.off_ev_ent = region(S * (size_t)P.ev_ent_stride * sizeof(JtEv));
+    P.off_fsig = region(S * (size_t)P.fsig_stride * sizeof(double));
+    P.off_fcnt = region(S * (size_t)P.fcnt_stride * sizeof(int32_t));
     P.total_bytes = off;
     std::string why;
     if (!verify_plan(P, why)) return fail(err, JT_E_ARG, why);

@@ -44,8 +44,8 @@ struct EdgeInfo {                    // edge (c, parent[c]); id = c
 };
 
 struct Launch {
-    int32_t is_pass;        // 1 = pass kernel over tasks, 0 = finalize over msgs
-    int32_t begin, count;   // tasks or msgs (per slot)
+    int32_t is_pass;        // 1 = pass kernel over tasks, 0 = finalize over ftasks, 2 = one-at-a-time set-up
+    int32_t begin, count;   // tasks or ftasks (per slot)
 };
 
 struct Plan {
@@ -64,6 +64,7 @@ struct Plan {
     std::vector<JtItem> items;
     std::vector<JtTask> tasks;
     std::vector<JtMsg> msgs;
+    std::vector<JtFTask> ftasks;
     std::vector<int32_t> child_edges;
     std::vector<Launch> fused;       // launch list of one fused propagation
     std::vector<Launch> plain;       // launch list of one one-at-a-time propagation
@@ -72,12 +73,12 @@ struct Plan {
     // per-slot region sizes (elements)
     int64_t init_floats = 0, coll_stride = 0, out_stride = 0, sep_stride = 0,
             partial_stride = 0, lam_stride = 0, scale_stride = 0, ev_idx_stride = 0,
-            ev_ent_stride = 0;
+            ev_ent_stride = 0, fsig_stride = 0, fcnt_stride = 0;
     // byte offsets of every region inside the workspace
     size_t off_meta = 0, off_views = 0, off_gathers = 0, off_items = 0, off_tasks = 0,
            off_msgs = 0, off_child = 0, off_init = 0, off_coll = 0, off_out = 0, off_sep = 0,
            off_partial = 0, off_lam = 0, off_scale = 0, off_flag = 0, off_ev_idx = 0,
-           off_ev_ent = 0, total_bytes = 0;
+           off_ev_ent = 0, off_ftasks = 0, off_fsig = 0, off_fcnt = 0, total_bytes = 0;
 
     // statistics
     int64_t total_entries = 0, entries_per_sweep = 0;
