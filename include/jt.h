@@ -69,10 +69,16 @@ typedef int32_t jt_status;
  *   JT_MODE_GRAPH  the same launches replayed from one captured HIP graph;
  *   JT_MODE_PLAIN  one message at a time in the paper's depth-first order
  *                  (Algorithms 2-3): marginalize, ratio, scatter launches per
- *                  message, tables updated in place. */
+ *                  message, tables updated in place;
+ *   JT_MODE_DATAFLOW  the fused passes as one persistent launch (replayed
+ *                  from a captured graph): blocks take the passes and
+ *                  finalizes of every slot in topological order and start
+ *                  each as soon as the messages it reads are complete, so
+ *                  tree levels overlap and no launch boundary separates them. */
 #define JT_MODE_FUSED 0
 #define JT_MODE_GRAPH 1
 #define JT_MODE_PLAIN 2
+#define JT_MODE_DATAFLOW 3
 
 typedef struct jt_tree_s *jt_tree;
 
@@ -121,9 +127,17 @@ jt_status jt_set_evidence(jt_tree t, int32_t slot, int32_t n_obs, const int32_t 
  * every table to the initial potentials with the slot's evidence entered,
  * collect to the root, distribute from it.  Asynchronous on the bound
  * stream; idempotent (always restarts from the initial potentials).
- *   mode  JT_MODE_FUSED, JT_MODE_GRAPH or JT_MODE_PLAIN.
- * Errors: JT_E_STATE (not bound), JT_E_ARG (mode), JT_E_HIP. */
+ *   mode  JT_MODE_FUSED, JT_MODE_GRAPH, JT_MODE_PLAIN or JT_MODE_DATAFLOW.
+ * Errors: JT_E_STATE (not bound), JT_E_ARG (mode), JT_E_HIP (also reported
+ * by the next jt_marginal when a dataflow dependency wait gave up). */
 jt_status jt_propagate(jt_tree t, int32_t mode);
+
+/* jt_propagate restricted to slots [0, n_active): the other slots are left
+ * as they are and their read-out calls return JT_E_STATE until a
+ * propagation covers them again.  A serving loop packs the queries of one
+ * batch into the first n_active slots.  Errors: as jt_propagate, and JT_E_ARG
+ * for n_active outside [1, n_slots]. */
+jt_status jt_propagate_n(jt_tree t, int32_t mode, int32_t n_active);
 
 /* Posterior of one clique, P(X_C | e) (Sec. 2.1: marginals are read from the
  * calibrated tables), normalized to sum 1, and log Z_e.  Synchronizes the
@@ -162,7 +176,12 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *     writes, all slots), JT_Q_BYTES_PLAIN (same for JT_MODE_PLAIN),
  *   JT_Q_N_LAUNCHES_FUSED, JT_Q_N_LAUNCHES_PLAIN (kernel launches per
  *     propagation), JT_Q_HEIGHT (levels of the collect sweep),
- *   JT_Q_DEPTH (levels of the distribute sweep).
+ *   JT_Q_DEPTH (levels of the distribute sweep),
+ *   JT_Q_FUSED_LAUNCH_KIND (arg = launch index: 1 pass, 0 finalize),
+ *   JT_Q_FUSED_LAUNCH_BYTES (arg = launch index: FP32 table bytes of a
+ *     pass launch, 0 for a finalize),
+ *   JT_Q_SLOT_BYTES (workspace bytes each slot adds),
+ *   JT_Q_SHARED_BYTES (workspace bytes independent of the slot count).
  * Errors: JT_E_ARG. */
 #define JT_Q_N_SLOTS 0
 #define JT_Q_TOTAL_ENTRIES 1
@@ -175,6 +194,10 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_N_LAUNCHES_PLAIN 8
 #define JT_Q_HEIGHT 9
 #define JT_Q_DEPTH 10
+#define JT_Q_FUSED_LAUNCH_KIND 11
+#define JT_Q_FUSED_LAUNCH_BYTES 12
+#define JT_Q_SLOT_BYTES 13
+#define JT_Q_SHARED_BYTES 14
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstring>
 #include <new>
 #include <string>
@@ -16,6 +17,8 @@
 hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, hipStream_t s);
 hipError_t jt_launch_finalize(const JtDev &d, int msg_begin, int n_msgs, int n_slots, hipStream_t s);
 hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s);
+hipError_t jt_launch_dataflow(const JtDev &d, int n_slots, int grid, hipStream_t s);
+int jt_dataflow_blocks_per_cu();
 
 namespace {
 
@@ -44,8 +47,11 @@ struct jt_tree_s {
     std::vector<char> ev_dirty;
     std::vector<int32_t> ev_idx_host;   // [n_slots][ev_idx_stride]
     std::vector<JtEv> ev_ent_host;      // [n_slots][ev_ent_stride]
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // captured graphs keyed by (schedule, active slots): 0 level launches, 1 dataflow
+    std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    int df_blocks = 1;    // resident blocks of the persistent kernel
+    int last_mode = -1;
+    int last_n_active = 0;
 };
 
 namespace {
@@ -80,8 +86,7 @@ jt_status upload_evidence(jt_tree t) {
     return JT_OK;
 }
 
-jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L) {
-    const int S = t->plan.n_slots;
+jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L, int S) {
     for (const jt::Launch &l : L) {
         hipError_t e = hipSuccess;
         if (l.is_pass == 2) {
@@ -97,10 +102,48 @@ jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L) {
 }
 
 void drop_graph(jt_tree t) {
-    if (t->gexec) (void)hipGraphExecDestroy(t->gexec);
-    if (t->graph) (void)hipGraphDestroy(t->graph);
-    t->gexec = nullptr;
-    t->graph = nullptr;
+    for (auto &kv : t->graphs) {
+        if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+        if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+    }
+    t->graphs.clear();
+}
+
+jt_status enqueue_dataflow(jt_tree t, int S) {
+    const int64_t units = std::max<int64_t>(1, (int64_t)t->plan.units.size() * S);
+    const int grid = (int)std::min<int64_t>(t->df_blocks, units);
+    hipError_t e = jt_launch_dataflow(t->dev, S, grid, t->stream);
+    if (e != hipSuccess) return hip_err(e, "dataflow launch");
+    return JT_OK;
+}
+
+// Capture the launches of one propagation once per (schedule, active
+// slots), then replay the graph.
+jt_status run_graph(jt_tree t, int k, int S) {
+    auto key = std::make_pair(k, S);
+    auto f = t->graphs.find(key);
+    if (f == t->graphs.end()) {
+        hipError_t e = hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_err(e, "begin capture");
+        jt_status rc = k == 0 ? enqueue(t, t->plan.fused, S) : enqueue_dataflow(t, S);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(t->stream, &g);
+        if (rc != JT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_err(e, "end capture");
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_err(e, "graph instantiate");
+        }
+        f = t->graphs.emplace(key, std::make_pair(g, x)).first;
+    }
+    hipError_t e = hipGraphLaunch(f->second.second, t->stream);
+    if (e != hipSuccess) return hip_err(e, "graph launch");
+    return JT_OK;
 }
 
 template <class T>
@@ -119,6 +162,12 @@ jt_status read_slot(jt_tree t, int32_t slot, double *log_z, bool *zero) {
     e = hipMemcpy(&lz, t->ws + P.off_lam + ((size_t)slot * P.lam_stride + JT_LAM_LOGZ(P.n_cliques)) * sizeof(double),
                   sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_err(e, "read log Z");
+    if (t->last_mode == JT_MODE_DATAFLOW) {
+        int32_t derr = 0;
+        e = hipMemcpy(&derr, t->ws + P.off_df + sizeof(int32_t), sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_err(e, "read dataflow status");
+        if (derr) return set_err(JT_E_HIP, "dataflow dependency wait timed out; results are invalid");
+    }
     *zero = flag != 0;
     if (log_z) *log_z = *zero ? -INFINITY : lz;
     return JT_OK;
@@ -182,6 +231,8 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     if (e == hipSuccess) e = up(P.off_msgs, P.msgs.data(), P.msgs.size() * sizeof(JtMsg));
     if (e == hipSuccess) e = up(P.off_child, P.child_edges.data(), P.child_edges.size() * sizeof(int32_t));
     if (e == hipSuccess) e = up(P.off_ftasks, P.ftasks.data(), P.ftasks.size() * sizeof(JtFTask));
+    if (e == hipSuccess) e = up(P.off_units, P.units.data(), P.units.size() * sizeof(JtUnit));
+    if (e == hipSuccess) e = up(P.off_deps, P.deps.data(), P.deps.size() * sizeof(int32_t));
     // finalize arrival counters start at zero; each finalize's last block
     // resets its counter, so no clearing is needed between propagations
     if (e == hipSuccess)
@@ -209,6 +260,21 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     d.fcnt = reinterpret_cast<int32_t *>(t->ws + P.off_fcnt);
     d.fsig_stride = P.fsig_stride;
     d.fcnt_stride = P.fcnt_stride;
+    d.units = region<JtUnit>(t, P.off_units);
+    d.deps = region<int32_t>(t, P.off_deps);
+    d.df = reinterpret_cast<int32_t *>(t->ws + P.off_df);
+    d.df_err = d.df + 1;
+    d.df_stride = P.df_stride;
+    d.n_items = P.n_fused_items;
+    d.n_units = (int32_t)P.units.size();
+    d.n_msgs = (int32_t)P.msgs.size();
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 1;
+        t->df_blocks = cus * jt_dataflow_blocks_per_cu();
+    }
     d.init = region<float>(t, P.off_init);
     d.coll = reinterpret_cast<float *>(t->ws + P.off_coll);
     d.out = reinterpret_cast<float *>(t->ws + P.off_out);
@@ -254,41 +320,31 @@ jt_status jt_set_evidence(jt_tree t, int32_t slot, int32_t n_obs, const int32_t 
     return JT_OK;
 }
 
-jt_status jt_propagate(jt_tree t, int32_t mode) {
+jt_status jt_propagate_n(jt_tree t, int32_t mode, int32_t n_active) {
     if (jt_status rc = check_tree(t)) return rc;
     if (!t->bound) return set_err(JT_E_STATE, "jt_propagate before jt_bind");
-    if (mode != JT_MODE_FUSED && mode != JT_MODE_GRAPH && mode != JT_MODE_PLAIN)
+    if (mode != JT_MODE_FUSED && mode != JT_MODE_GRAPH && mode != JT_MODE_PLAIN && mode != JT_MODE_DATAFLOW)
         return set_err(JT_E_ARG, "unknown mode");
+    if (n_active < 1 || n_active > t->plan.n_slots) return set_err(JT_E_ARG, "n_active out of range");
     if (jt_status rc = upload_evidence(t)) return rc;
     jt_status rc = JT_OK;
-    if (mode == JT_MODE_FUSED) {
-        rc = enqueue(t, t->plan.fused);
-    } else if (mode == JT_MODE_PLAIN) {
-        rc = enqueue(t, t->plan.plain);
-    } else {
-        if (!t->gexec) {
-            hipError_t e = hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return hip_err(e, "begin capture");
-            rc = enqueue(t, t->plan.fused);
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(t->stream, &g);
-            if (rc != JT_OK) {
-                if (g) (void)hipGraphDestroy(g);
-                return rc;
-            }
-            if (e != hipSuccess) return hip_err(e, "end capture");
-            t->graph = g;
-            e = hipGraphInstantiate(&t->gexec, g, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                drop_graph(t);
-                return hip_err(e, "graph instantiate");
-            }
-        }
-        hipError_t e = hipGraphLaunch(t->gexec, t->stream);
-        if (e != hipSuccess) return hip_err(e, "graph launch");
+    if (mode == JT_MODE_FUSED)
+        rc = enqueue(t, t->plan.fused, n_active);
+    else if (mode == JT_MODE_PLAIN)
+        rc = enqueue(t, t->plan.plain, n_active);
+    else
+        rc = run_graph(t, mode == JT_MODE_GRAPH ? 0 : 1, n_active);
+    if (rc == JT_OK) {
+        t->propagated = true;
+        t->last_mode = mode;
+        t->last_n_active = n_active;
     }
-    if (rc == JT_OK) t->propagated = true;
     return rc;
+}
+
+jt_status jt_propagate(jt_tree t, int32_t mode) {
+    if (jt_status rc = check_tree(t)) return rc;
+    return jt_propagate_n(t, mode, t->plan.n_slots);
 }
 
 jt_status jt_marginal(jt_tree t, int32_t slot, int32_t clique, float *out, double *log_z) {
@@ -297,6 +353,7 @@ jt_status jt_marginal(jt_tree t, int32_t slot, int32_t clique, float *out, doubl
     if (slot < 0 || slot >= P.n_slots) return set_err(JT_E_ARG, "slot out of range");
     if (clique < 0 || clique >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");
     if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+    if (slot >= t->last_n_active) return set_err(JT_E_STATE, "slot was not active in the last propagation");
     bool zero = false;
     if (jt_status rc = read_slot(t, slot, log_z, &zero)) return rc;
     if (zero) return set_err(JT_E_ZERO_EVIDENCE, "evidence has probability zero");
@@ -314,6 +371,7 @@ jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z) {
     const jt::Plan &P = t->plan;
     if (slot < 0 || slot >= P.n_slots) return set_err(JT_E_ARG, "slot out of range");
     if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+    if (slot >= t->last_n_active) return set_err(JT_E_STATE, "slot was not active in the last propagation");
     bool zero = false;
     if (jt_status rc = read_slot(t, slot, log_z, &zero)) return rc;
     if (zero) return set_err(JT_E_ZERO_EVIDENCE, "evidence has probability zero");
@@ -387,6 +445,17 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
         case JT_Q_N_LAUNCHES_PLAIN: *out = nlaunch(P.plain); break;
         case JT_Q_HEIGHT: *out = P.height + 1; break;
         case JT_Q_DEPTH: *out = P.depth + 1; break;
+        case JT_Q_SLOT_BYTES: *out = (int64_t)P.slot_bytes; break;
+        case JT_Q_SHARED_BYTES: *out = (int64_t)P.total_bytes - (int64_t)P.slot_bytes * P.n_slots; break;
+        case JT_Q_FUSED_LAUNCH_KIND:
+        case JT_Q_FUSED_LAUNCH_BYTES: {
+            std::vector<const jt::Launch *> live;
+            for (const jt::Launch &l : P.fused)
+                if (l.count > 0) live.push_back(&l);
+            if (arg < 0 || arg >= (int64_t)live.size()) return set_err(JT_E_ARG, "launch index out of range");
+            *out = what == JT_Q_FUSED_LAUNCH_KIND ? live[arg]->is_pass : live[arg]->bytes;
+            break;
+        }
         default: return set_err(JT_E_ARG, "unknown query");
     }
     return JT_OK;
@@ -396,10 +465,39 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
                      int32_t *n_finalize) {
     if (jt_status rc = check_tree(t)) return rc;
     if (!t->bound) return set_err(JT_E_STATE, "jt_profile before jt_bind");
-    if (mode != JT_MODE_FUSED && mode != JT_MODE_PLAIN) return set_err(JT_E_ARG, "profile mode must be fused or plain");
+    if (mode != JT_MODE_FUSED && mode != JT_MODE_PLAIN && mode != JT_MODE_DATAFLOW)
+        return set_err(JT_E_ARG, "profile mode must be fused, plain or dataflow");
     if (jt_status rc = upload_evidence(t)) return rc;
+    if (mode == JT_MODE_DATAFLOW) {
+        // the persistent launch is the pass; its counter reset is reported
+        // as the finalize share
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+        if (e == hipSuccess) e = hipEventRecord(ev[0], t->stream);
+        if (e == hipSuccess) {
+            const int64_t units = std::max<int64_t>(1, (int64_t)t->plan.units.size() * t->plan.n_slots);
+            e = jt_launch_dataflow(t->dev, t->plan.n_slots, (int)std::min<int64_t>(t->df_blocks, units), t->stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[2], t->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[2]);
+        for (int k = 0; k < 3; ++k)
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+        if (e != hipSuccess) return hip_err(e, "profiled dataflow launch");
+        t->propagated = true;
+        t->last_mode = mode;
+        t->last_n_active = t->plan.n_slots;
+        if (pass_ms) *pass_ms = ms;
+        if (finalize_ms) *finalize_ms = 0.0;
+        if (n_pass) *n_pass = 1;
+        if (n_finalize) *n_finalize = 0;
+        return JT_OK;
+    }
     const std::vector<jt::Launch> &L = mode == JT_MODE_FUSED ? t->plan.fused : t->plan.plain;
     const int S = t->plan.n_slots;
+    t->last_n_active = S;
     std::vector<hipEvent_t> ev;
     std::vector<int> kind;
     jt_status rc = JT_OK;
@@ -455,6 +553,7 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
     for (hipEvent_t x : ev) (void)hipEventDestroy(x);
     if (rc != JT_OK) return rc;
     t->propagated = true;
+    t->last_mode = mode;
     if (pass_ms) *pass_ms = tp;
     if (finalize_ms) *finalize_ms = tf;
     if (n_pass) *n_pass = np;

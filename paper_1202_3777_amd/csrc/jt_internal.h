@@ -69,7 +69,10 @@ typedef struct {
     // the output view's reduction tables, copied here to keep the kernel
     // prologue short (meta offsets stay below 2^30)
     int32_t o_kout_tile, o_kout_j, o_rout_tile, o_perm, o_clsj;
-    int32_t o_n_rout, o_n_cls, o_m_in, o_ssize, pad;
+    int32_t o_n_rout, o_n_cls, o_m_in, o_ssize;
+    // dataflow schedule: messages this pass needs finalized first, and the
+    // number of tasks (blocks) that make up the pass
+    int32_t dep_base, n_dep, n_tasks, pad;
 } JtItem;
 
 // A block's share of an item: groups [g0, g1), spread over the block's waves.
@@ -96,7 +99,14 @@ typedef struct {
     int32_t child_base, n_children;  // children edges of `from` (collect log-scale sum)
     int32_t sepc_off, sepd_off;      // separator tables in the per-slot region
     int32_t fbase, nfb;              // finalize blocks: per-slot sigma scratch index, count
+    int32_t item, pad;               // the pass item whose partials this message sums
 } JtMsg;
+
+// One unit of the dataflow schedule: a pass task or a finalize task.
+typedef struct {
+    int32_t kind;    // 0 = pass task, 1 = finalize task
+    int32_t index;   // into tasks or ftasks
+} JtUnit;
 
 // A block's share of one message's finalize: separator entries [j0, j1),
 // jc columns by JT_BLOCK / jc split rows; block b of nb for the message.
@@ -138,10 +148,14 @@ typedef struct {
     int32_t *flag;
     double *fsig;                  // per-slot block sums of the finalize
     int32_t *fcnt;                 // per-slot arrival counters, one per message
+    const JtUnit *units;           // dataflow schedule
+    const int32_t *deps;           // message indices the items depend on
+    int32_t *df;                   // [0] next unit; then per slot: item done counts, message done flags
+    int32_t *df_err;               // set when a dependency wait gives up
     const int32_t *ev_idx;
     const JtEv *ev_ent;
     int64_t coll_stride, out_stride, sep_stride, partial_stride;
     int64_t lam_stride, scale_stride, ev_idx_stride, ev_ent_stride;
-    int64_t fsig_stride, fcnt_stride;
-    int32_t n_cliques, pad;
+    int64_t fsig_stride, fcnt_stride, df_stride;
+    int32_t n_cliques, n_items, n_units, n_msgs;
 } JtDev;

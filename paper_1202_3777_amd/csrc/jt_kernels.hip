@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "jt_internal.h"
 
 namespace {
@@ -117,7 +119,11 @@ __device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, 
         }
     }
 
-    const float scale = it.scale_clique >= 0 ? scale_arr[(int64_t)slot * st.scale + it.scale_clique] : 1.0f;
+    // written by a finalize earlier in the same dataflow launch: a coherent
+    // (vector) load, never the scalar cache
+    const float scale = it.scale_clique >= 0 ? __hip_atomic_load(scale_arr + (int64_t)slot * st.scale + it.scale_clique,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                             : 1.0f;
     const float *src =
         (it.src_kind == JT_SRC_INIT ? init
                                     : (it.src_kind == JT_SRC_COLL ? coll + (int64_t)slot * st.coll
@@ -306,22 +312,34 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
 // block sum to the message's scratch.  The block that arrives last forms
 // sigma from the block sums in block order, updates the log-scales, and
 // rescales the whole separator table (and forms new/old, 0/0 := 0).
-extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev d, int ftask_begin, int n_ftasks) {
-    __shared__ float red[JT_BLOCK];
-    __shared__ double dred[JT_BLOCK];
-    __shared__ float sh_f;
-    __shared__ int sh_last;
+// Returns true in the block that completed the message.
+namespace {
+
+struct FinPtrs {
+    const JtMsg *__restrict__ msgs;
+    const int32_t *__restrict__ child_edges;
+    const float *__restrict__ partial;
+    float *__restrict__ sep;
+    double *__restrict__ lam;
+    float *__restrict__ scale;
+    int32_t *__restrict__ flag;
+    double *__restrict__ fsig;
+    int32_t *__restrict__ fcnt;
+    int64_t partial_stride, sep_stride, lam_stride, scale_stride, fsig_stride, fcnt_stride;
+    int32_t n_cliques;
+};
+
+__device__ bool finalize_block(const FinPtrs &F, const JtFTask &ft, int slot, float *red, double *dred, float *sh_f,
+                               int *sh_last) {
     const int tid = threadIdx.x;
-    const int slot = blockIdx.x / n_ftasks;
-    const JtFTask ft = d.ftasks[ftask_begin + (blockIdx.x - slot * n_ftasks)];
-    const JtMsg m = d.msgs[ft.msg];
-    const int nc = d.n_cliques;
-    const float *P = d.partial + (int64_t)slot * d.partial_stride + m.partial_off;
-    float *sep = d.sep + (int64_t)slot * d.sep_stride;
-    double *lam = d.lam + (int64_t)slot * d.lam_stride;
-    float *scl = d.scale + (int64_t)slot * d.scale_stride;
-    double *fsig = d.fsig + (int64_t)slot * d.fsig_stride;
-    int32_t *fcnt = d.fcnt + (int64_t)slot * d.fcnt_stride;
+    const JtMsg m = F.msgs[ft.msg];
+    const int nc = F.n_cliques;
+    const float *P = F.partial + (int64_t)slot * F.partial_stride + m.partial_off;
+    float *sep = F.sep + (int64_t)slot * F.sep_stride;
+    double *lam = F.lam + (int64_t)slot * F.lam_stride;
+    float *scl = F.scale + (int64_t)slot * F.scale_stride;
+    double *fsig = F.fsig + (int64_t)slot * F.fsig_stride;
+    int32_t *fcnt = F.fcnt + (int64_t)slot * F.fcnt_stride;
     const int ssize = m.ssize, nsplit = m.nsplit;
     float *raw = nullptr;
     if (m.kind == JT_MSG_COLLECT) raw = sep + m.sepc_off;
@@ -365,9 +383,13 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev 
         if (tid == 0) fsig[m.fbase + ft.b] = dred[0];
         __threadfence();
         __syncthreads();
-        if (tid == 0) sh_last = (atomicAdd(&fcnt[ft.msg], 1) == ft.nb - 1);
+        if (tid == 0) {
+            __threadfence();
+            *sh_last = (atomicAdd(&fcnt[ft.msg], 1) == ft.nb - 1);
+            __threadfence();
+        }
         __syncthreads();
-        if (!sh_last) return;
+        if (!*sh_last) return false;
         __threadfence();
     }
     if (tid == 0) {
@@ -382,7 +404,7 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev 
         switch (m.kind) {
             case JT_MSG_COLLECT: {
                 double lc = 0.0;
-                for (int a = 0; a < m.n_children; ++a) lc += lam[JT_LAM_SC(nc) + d.child_edges[m.child_base + a]];
+                for (int a = 0; a < m.n_children; ++a) lc += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
                 lam[JT_LAM_COLL(nc) + m.from] = lc;
                 if (sigma > 0.0) {
                     f = ns / sigma;
@@ -394,16 +416,16 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev 
             }
             case JT_MSG_TOTAL: {
                 double lc = 0.0;
-                for (int a = 0; a < m.n_children; ++a) lc += lam[JT_LAM_SC(nc) + d.child_edges[m.child_base + a]];
+                for (int a = 0; a < m.n_children; ++a) lc += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
                 lam[JT_LAM_COLL(nc) + m.from] = lc;
                 if (sigma > 0.0) {
                     lam[JT_LAM_LOGZ(nc)] = lc + log(sigma);
                     scl[m.from] = (float)(1.0 / sigma);
-                    d.flag[slot] = 0;
+                    F.flag[slot] = 0;
                 } else {
                     lam[JT_LAM_LOGZ(nc)] = -INFINITY;
                     scl[m.from] = 0.f;
-                    d.flag[slot] = 1;
+                    F.flag[slot] = 1;
                 }
                 break;
             }
@@ -434,15 +456,15 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev 
                 scl[m.from] = sigma > 0.0 ? (float)(1.0 / sigma) : 0.f;
                 if (m.to == -2) {
                     lam[JT_LAM_LOGZ(nc)] = sigma > 0.0 ? lam[JT_LAM_COLL(nc) + m.from] + log(sigma) : -INFINITY;
-                    d.flag[slot] = sigma > 0.0 ? 0 : 1;
+                    F.flag[slot] = sigma > 0.0 ? 0 : 1;
                 }
                 break;
             }
         }
-        sh_f = (float)f;
+        *sh_f = (float)f;
     }
     __syncthreads();
-    const float f = sh_f;
+    const float f = *sh_f;
     if (m.kind == JT_MSG_COLLECT) {
         for (int jx = tid; jx < ssize; jx += JT_BLOCK) raw[jx] = raw[jx] * f;
     } else if (m.kind == JT_MSG_DIST) {
@@ -461,6 +483,168 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev 
             oldc[jx] = nw;
         }
     }
+    return true;
+}
+
+__device__ __forceinline__ FinPtrs fin_ptrs(const JtDev &d) {
+    FinPtrs F;
+    F.msgs = d.msgs;
+    F.child_edges = d.child_edges;
+    F.partial = d.partial;
+    F.sep = d.sep;
+    F.lam = d.lam;
+    F.scale = d.scale;
+    F.flag = d.flag;
+    F.fsig = d.fsig;
+    F.fcnt = d.fcnt;
+    F.partial_stride = d.partial_stride;
+    F.sep_stride = d.sep_stride;
+    F.lam_stride = d.lam_stride;
+    F.scale_stride = d.scale_stride;
+    F.fsig_stride = d.fsig_stride;
+    F.fcnt_stride = d.fcnt_stride;
+    F.n_cliques = d.n_cliques;
+    return F;
+}
+
+}  // namespace
+
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev d, int ftask_begin, int n_ftasks) {
+    __shared__ float red[JT_BLOCK];
+    __shared__ double dred[JT_BLOCK];
+    __shared__ float sh_f;
+    __shared__ int sh_last;
+    const int slot = blockIdx.x / n_ftasks;
+    const JtFTask ft = d.ftasks[ftask_begin + (blockIdx.x - slot * n_ftasks)];
+    finalize_block(fin_ptrs(d), ft, slot, red, dred, &sh_f, &sh_last);
+}
+
+// Dataflow schedule: one persistent launch for the whole propagation.  Blocks
+// take units (a pass task or a finalize task, for one slot) from a global
+// counter in topological order and wait only for what that unit reads: a
+// pass task for the finalize of the messages whose tables it multiplies in
+// (and whose scale it applies), a finalize task for every task of the pass
+// that produced its partials.  A unit only ever waits for units taken
+// before it, so the smallest unfinished unit can always run and every block
+// reaches the end.  A wait that exceeds its bound sets df_err and gives up,
+// so the launch still ends.
+#define JT_SPIN_LIMIT (1 << 20)
+
+__device__ __forceinline__ bool wait_at_least(int32_t *p, int32_t want) {
+    for (int it = 0; it < JT_SPIN_LIMIT; ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
+
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_dataflow_kernel(
+    const JtUnit *__restrict__ units, const int32_t *__restrict__ deps, const JtTask *__restrict__ tasks,
+    const JtItem *__restrict__ items, const JtGather *__restrict__ gathers, const int32_t *__restrict__ meta,
+    const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent, const float *__restrict__ init,
+    float *__restrict__ coll, float *__restrict__ out, float *__restrict__ sep, float *__restrict__ scale,
+    float *__restrict__ partial, const JtFTask *__restrict__ ftasks, const JtMsg *__restrict__ msgs,
+    const int32_t *__restrict__ child_edges, double *__restrict__ lam, int32_t *__restrict__ flag,
+    double *__restrict__ fsig, int32_t *__restrict__ fcnt, int32_t *__restrict__ df, int32_t *__restrict__ df_err,
+    PassStrides st, int64_t lam_stride, int64_t fsig_stride, int64_t fcnt_stride, int64_t df_stride, int n_cliques,
+    int n_items, int n_units, int n_slots) {
+    __shared__ float lds_ratio[JT_LDS_RATIO_FLOATS];
+    __shared__ float lds_red[JT_WAVES_PER_BLOCK][JT_TILE_MAX];
+    __shared__ double dred[JT_BLOCK];
+    __shared__ float sh_f;
+    __shared__ int sh_last, sh_unit, sh_ok;
+    FinPtrs F;
+    F.msgs = msgs;
+    F.child_edges = child_edges;
+    F.partial = partial;
+    F.sep = sep;
+    F.lam = lam;
+    F.scale = scale;
+    F.flag = flag;
+    F.fsig = fsig;
+    F.fcnt = fcnt;
+    F.partial_stride = st.partial;
+    F.sep_stride = st.sep;
+    F.lam_stride = lam_stride;
+    F.scale_stride = st.scale;
+    F.fsig_stride = fsig_stride;
+    F.fcnt_stride = fcnt_stride;
+    F.n_cliques = n_cliques;
+    const int tid = threadIdx.x;
+    const int total = n_units * n_slots;
+    for (;;) {
+        if (tid == 0) sh_unit = atomicAdd(&df[0], 1);
+        __syncthreads();
+        const int g = sh_unit;
+        __syncthreads();
+        if (g >= total) break;
+        const int u = g / n_slots, slot = g - u * n_slots;
+        const JtUnit U = units[u];
+        int32_t *done = df + JT_WAVE + (int64_t)slot * df_stride;   // [0, n_items) items, then messages
+        if (U.kind == 0) {
+            const JtTask task = tasks[U.index];
+            const JtItem it = items[task.item];
+            if (tid == 0) {
+                bool ok = true;
+                for (int a = 0; a < it.n_dep && ok; ++a) ok = wait_at_least(done + n_items + deps[it.dep_base + a], 1);
+                if (!ok) atomicExch(df_err, 1);
+                sh_ok = ok;
+                __threadfence();   // acquire: what the producers released is visible
+            }
+            __syncthreads();
+            __threadfence();
+            if (sh_ok) {
+                const float *sep_slot = sep + (int64_t)slot * st.sep;
+                for (int gg = 0; gg < it.n_gather_lds; ++gg) {
+                    const JtGather G = gathers[it.gather_base + gg];
+                    for (int j = tid; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = sep_slot[G.sep_off + j];
+                }
+                __syncthreads();
+                float *red = lds_red[tid / JT_WAVE];
+                if (it.vec == 4)
+                    pass_body<4>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial,
+                                 st, lds_ratio, red);
+                else
+                    pass_body<1>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial,
+                                 st, lds_ratio, red);
+            }
+            __threadfence();   // release this block's table and partial writes
+            __syncthreads();
+            if (tid == 0) {
+                __threadfence();
+                atomicAdd(done + task.item, 1);
+            }
+        } else {
+            const JtFTask ft = ftasks[U.index];
+            const JtMsg m = msgs[ft.msg];
+            if (tid == 0) {
+                const bool ok = wait_at_least(done + m.item, items[m.item].n_tasks);
+                if (!ok) atomicExch(df_err, 1);
+                sh_ok = ok;
+                __threadfence();
+            }
+            __syncthreads();
+            __threadfence();
+            bool last = false;
+            if (sh_ok) last = finalize_block(F, ft, slot, lds_red[0], dred, &sh_f, &sh_last);
+            if (!sh_ok) last = (ft.b == 0);   // a failed wait still releases the dependents
+            __threadfence();
+            __syncthreads();
+            if (last && tid == 0) {
+                __threadfence();
+                atomicExch(done + n_items + ft.msg, 1);
+            }
+        }
+    }
+}
+
+// Clears the dataflow counters before the persistent launch (a kernel, so
+// the propagation can be captured in a graph without memset nodes).
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_dataflow_reset_kernel(int32_t *df, int64_t n, int32_t *fcnt,
+                                                                                int64_t n_fcnt) {
+    for (int64_t i = blockIdx.x * (int64_t)JT_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * JT_BLOCK) df[i] = 0;
+    for (int64_t i = blockIdx.x * (int64_t)JT_BLOCK + threadIdx.x; i < n_fcnt; i += (int64_t)gridDim.x * JT_BLOCK)
+        fcnt[i] = 0;
 }
 
 // One-at-a-time schedule set-up: every separator table := 1, log-scales := 0.
@@ -494,6 +678,36 @@ hipError_t jt_launch_finalize(const JtDev &d, int ftask_begin, int n_ftasks, int
     hipLaunchKernelGGL(jt_finalize_kernel, dim3((unsigned)n_ftasks * (unsigned)n_slots), dim3(JT_BLOCK), 0, s, d,
                        ftask_begin, n_ftasks);
     return hipGetLastError();
+}
+
+hipError_t jt_launch_dataflow(const JtDev &d, int n_slots, int grid, hipStream_t s) {
+    const int64_t n_df = JT_WAVE + (int64_t)n_slots * d.df_stride;
+    hipLaunchKernelGGL(jt_dataflow_reset_kernel, dim3((unsigned)std::min<int64_t>(1024, (n_df + JT_BLOCK - 1) / JT_BLOCK)),
+                       dim3(JT_BLOCK), 0, s, d.df, n_df, d.fcnt, (int64_t)n_slots * d.fcnt_stride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PassStrides st;
+    st.coll = d.coll_stride;
+    st.out = d.out_stride;
+    st.sep = d.sep_stride;
+    st.partial = d.partial_stride;
+    st.scale = d.scale_stride;
+    st.ev_idx = d.ev_idx_stride;
+    st.ev_ent = d.ev_ent_stride;
+    hipLaunchKernelGGL(jt_dataflow_kernel, dim3((unsigned)grid), dim3(JT_BLOCK), 0, s, d.units, d.deps, d.tasks,
+                       d.items, d.gathers, d.meta, d.ev_idx, d.ev_ent, d.init, d.coll, d.out, d.sep, d.scale,
+                       d.partial, d.ftasks, d.msgs, d.child_edges, d.lam, d.flag, d.fsig, d.fcnt, d.df, d.df + 1, st,
+                       d.lam_stride, d.fsig_stride, d.fcnt_stride, d.df_stride, d.n_cliques, d.n_items, d.n_units,
+                       n_slots);
+    return hipGetLastError();
+}
+
+int jt_dataflow_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(jt_dataflow_kernel), JT_BLOCK,
+                                                     0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
 }
 
 hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s) {

@@ -203,6 +203,7 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1) {
         JT_WAVES_PER_BLOCK, (per + JT_WAVES_PER_BLOCK - 1) / JT_WAVES_PER_BLOCK * JT_WAVES_PER_BLOCK);
     for (int32_t i = i0; i < i1; ++i)
         for (int32_t g0 = 0; g0 < P.items[i].n_groups; g0 += gpb) {
+            P.items[i].n_tasks++;
             JtTask t;
             t.item = i;
             t.g0 = g0;
@@ -433,6 +434,36 @@ bool verify_plan(const Plan &P, std::string &why) {
         if (m.fbase < 0 || m.fbase + m.nfb > P.fsig_stride) return bad("finalize scratch");
     }
     if ((int64_t)P.msgs.size() > P.fcnt_stride) return bad("finalize counters");
+    for (const JtUnit &u : P.units) {
+        if (u.kind == 0 && (u.index < 0 || u.index >= (int32_t)P.tasks.size() || P.tasks[u.index].item >= P.n_fused_items))
+            return bad("unit task");
+        if (u.kind == 1 && (u.index < 0 || u.index >= (int32_t)P.ftasks.size())) return bad("unit ftask");
+    }
+    // every dependency points to a message finalized by an earlier unit
+    {
+        std::vector<int32_t> done_at(P.msgs.size(), -1);
+        for (size_t k = 0; k < P.units.size(); ++k)
+            if (P.units[k].kind == 1) done_at[P.ftasks[P.units[k].index].msg] = (int32_t)k;
+        for (size_t k = 0; k < P.units.size(); ++k) {
+            if (P.units[k].kind != 0) continue;
+            const JtItem &it = P.items[P.tasks[P.units[k].index].item];
+            if (it.dep_base < 0 || it.dep_base + it.n_dep > (int32_t)P.deps.size()) return bad("dependency range");
+            for (int32_t a = 0; a < it.n_dep; ++a) {
+                const int32_t mi = P.deps[it.dep_base + a];
+                if (mi < 0 || mi >= (int32_t)P.msgs.size() || done_at[mi] < 0 || done_at[mi] >= (int32_t)k)
+                    return bad("dependency order");
+            }
+        }
+        for (size_t k = 0; k < P.units.size(); ++k) {
+            if (P.units[k].kind != 1) continue;
+            const JtMsg &m = P.msgs[P.ftasks[P.units[k].index].msg];
+            if (m.item < 0 || m.item >= P.n_fused_items) return bad("message item");
+            int32_t seen = 0;
+            for (size_t q = 0; q < k; ++q)
+                if (P.units[q].kind == 0 && P.tasks[P.units[q].index].item == m.item) ++seen;
+            if (seen != P.items[m.item].n_tasks) return bad("message item tasks");
+        }
+    }
     for (const std::vector<Launch> *L : {&P.fused, &P.plain})
         for (const Launch &l : *L) {
             if (l.is_pass == 1 && (l.begin < 0 || l.begin + l.count > (int32_t)P.tasks.size())) return bad("launch tasks");
@@ -606,6 +637,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     }
     int64_t bytes = 0;
     int64_t fsig_count = 0;
+    std::vector<int32_t> coll_msg(nc, -1), dist_msg(nc, -1);   // message into each clique's parent / from it
     for (int32_t h = 0; h <= P.height; ++h) {
         const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
         int64_t level_entries = 0;
@@ -622,11 +654,16 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             // item first with a placeholder, then patch its offset.
             const int32_t it = add_item(P, c, JT_SRC_INIT, C.init_off, C.children.empty() ? JT_DST_NONE : JT_DST_COLL,
                                         C.coll_off, gs, -1, view, 0, bytes, ge);
+            P.items[it].dep_base = (int32_t)P.deps.size();
+            for (int32_t ch : C.children) P.deps.push_back(coll_msg[ch]);
+            P.items[it].n_dep = (int32_t)C.children.size();
+            coll_msg[c] = m0 + (int32_t)level_msgs.size();
             const int64_t ss = P.views[view].ssize;
             const int64_t poff = add_partial(ss * item_nsplit(P, it));
             P.items[it].partial_off = poff;
             JtMsg m;
             std::memset(&m, 0, sizeof(m));
+            m.item = it;
             m.kind = is_root ? JT_MSG_TOTAL : JT_MSG_COLLECT;
             m.edge = is_root ? -1 : c;
             m.from = c;
@@ -662,8 +699,16 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             const bool leaf = C.children.empty();
             const int32_t src_kind = leaf ? JT_SRC_INIT : JT_SRC_COLL;
             const int64_t src_off = leaf ? C.init_off : C.coll_off;
+            // every distribute pass of c waits for the message that gives c
+            // its output scale: parent -> c, or the root's total
+            const int32_t dep = (c == P.root) ? coll_msg[c] : dist_msg[c];
+            auto set_dep = [&](int32_t item) {
+                P.items[item].dep_base = (int32_t)P.deps.size();
+                P.deps.push_back(dep);
+                P.items[item].n_dep = 1;
+            };
             if (leaf) {
-                add_item(P, c, src_kind, src_off, JT_DST_OUT, C.out_off, gs, c, -1, 0, bytes, ge);
+                set_dep(add_item(P, c, src_kind, src_off, JT_DST_OUT, C.out_off, gs, c, -1, 0, bytes, ge));
                 continue;
             }
             for (size_t k = 0; k < C.children.size(); ++k) {
@@ -671,11 +716,14 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                 const int32_t view = P.edge[ch].view_parent;
                 const int32_t it = add_item(P, c, src_kind, src_off, k == 0 ? JT_DST_OUT : JT_DST_NONE,
                                             C.out_off, gs, c, view, 0, bytes, ge);
+                set_dep(it);
+                dist_msg[ch] = m0 + (int32_t)level_msgs.size();
                 const int64_t ss = P.views[view].ssize;
                 const int64_t poff = add_partial(ss * item_nsplit(P, it));
                 P.items[it].partial_off = poff;
                 JtMsg m;
                 std::memset(&m, 0, sizeof(m));
+                m.item = it;
                 m.kind = JT_MSG_DIST;
                 m.edge = ch;
                 m.from = c;
@@ -696,6 +744,11 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         if (!level_msgs.empty()) P.fused.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
     }
     P.bytes_fused = bytes;
+
+    // dataflow order: the fused launches' tasks and finalize tasks, in order
+    for (const Launch &l : P.fused)
+        for (int32_t x = l.begin; x < l.begin + l.count; ++x) P.units.push_back({l.is_pass ? 0 : 1, x});
+    P.n_fused_items = (int32_t)P.items.size();
 
     // ---------------- one-message-at-a-time schedule ----------------
     // Tables live in the output region and are updated in place.
@@ -806,6 +859,20 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
     }
     P.bytes_plain = bytes;
+    for (std::vector<Launch> *L : {&P.fused, &P.plain})
+        for (Launch &l : *L) {
+            if (l.is_pass != 1 || l.count == 0) continue;
+            int32_t last = -1;
+            for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
+                const int32_t i = P.tasks[t].item;
+                if (i == last) continue;
+                last = i;
+                const JtItem &it = P.items[i];
+                const int64_t tb = 4 * P.cl[it.clique].size;
+                l.bytes += (it.src_kind == JT_SRC_INIT) ? tb : tb * P.n_slots;
+                if (it.dst_kind != JT_DST_NONE) l.bytes += tb * P.n_slots;
+            }
+        }
     if (P.partial_stride > std::numeric_limits<int32_t>::max() * int64_t(4))
         return fail(err, JT_E_TOO_LARGE, "partial region too large");
 
@@ -841,9 +908,19 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_flag = region(S * sizeof(int32_t));
     P.off_ev_idx = region(S * (size_t)P.ev_idx_stride * sizeof(int32_t));
     P.off_ev_ent = region(S * (size_t)P.ev_ent_stride * sizeof(JtEv));
+    P.off_units = region(std::max<size_t>(1, P.units.size()) * sizeof(JtUnit));
+    P.off_deps = region(std::max<size_t>(1, P.deps.size()) * sizeof(int32_t));
+    P.df_stride = align_up((int64_t)P.n_fused_items + (int64_t)P.msgs.size(), kAlignFloats);
+    P.off_df = region((size_t)(kAlignFloats + S * P.df_stride) * sizeof(int32_t));
     P.off_fsig = region(S * (size_t)P.fsig_stride * sizeof(double));
     P.off_fcnt = region(S * (size_t)P.fcnt_stride * sizeof(int32_t));
     P.total_bytes = off;
+    P.slot_bytes = (size_t)P.coll_stride * sizeof(float) + (size_t)P.out_stride * sizeof(float) +
+                   (size_t)P.sep_stride * sizeof(float) + (size_t)P.partial_stride * sizeof(float) +
+                   (size_t)P.lam_stride * sizeof(double) + (size_t)P.scale_stride * sizeof(float) + sizeof(int32_t) +
+                   (size_t)P.ev_idx_stride * sizeof(int32_t) + (size_t)P.ev_ent_stride * sizeof(JtEv) +
+                   (size_t)P.fsig_stride * sizeof(double) + (size_t)P.fcnt_stride * sizeof(int32_t) +
+                   (size_t)P.df_stride * sizeof(int32_t);
     std::string why;
     if (!verify_plan(P, why)) return fail(err, JT_E_ARG, why);
     return JT_OK;

@@ -28,7 +28,8 @@ JT_E_STATE = -7
 JT_MODE_FUSED = 0
 JT_MODE_GRAPH = 1
 JT_MODE_PLAIN = 2
-MODES = {"fused": JT_MODE_FUSED, "graph": JT_MODE_GRAPH, "plain": JT_MODE_PLAIN}
+JT_MODE_DATAFLOW = 3
+MODES = {"fused": JT_MODE_FUSED, "graph": JT_MODE_GRAPH, "plain": JT_MODE_PLAIN, "dataflow": JT_MODE_DATAFLOW}
 
 JT_Q_N_SLOTS = 0
 JT_Q_TOTAL_ENTRIES = 1
@@ -41,8 +42,12 @@ JT_Q_N_LAUNCHES_FUSED = 7
 JT_Q_N_LAUNCHES_PLAIN = 8
 JT_Q_HEIGHT = 9
 JT_Q_DEPTH = 10
+JT_Q_FUSED_LAUNCH_KIND = 11
+JT_Q_FUSED_LAUNCH_BYTES = 12
+JT_Q_SLOT_BYTES = 13
+JT_Q_SHARED_BYTES = 14
 
-EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_marginal",
+EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
             "jt_free", "jt_last_error"]
 
@@ -79,13 +84,14 @@ def load():
     lib.jt_bind.argtypes = [V, V, SZ, V, V]
     lib.jt_set_evidence.argtypes = [V, I32, I32, P32, P32]
     lib.jt_propagate.argtypes = [V, I32]
+    lib.jt_propagate_n.argtypes = [V, I32, I32]
     lib.jt_marginal.argtypes = [V, I32, I32, V, PD]
     lib.jt_marginals_all.argtypes = [V, I32, V, PD]
     lib.jt_get_index_map.argtypes = [V, I32, I32, P32]
     lib.jt_get_mu_lists.argtypes = [V, I32, I32, P32]
     lib.jt_query.argtypes = [V, I32, I64, P64]
     lib.jt_profile.argtypes = [V, I32, PD, PD, P32, P32]
-    for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_marginal",
+    for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
               "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile"):
         getattr(lib, f).restype = I32
     lib.jt_free.argtypes = [V]
@@ -140,6 +146,10 @@ def jt_set_evidence(h, slot: int, vars: Sequence[int], states: Sequence[int]):
 
 def jt_propagate(h, mode: int = JT_MODE_FUSED):
     _check(load().jt_propagate(h, int(mode)), "jt_propagate")
+
+
+def jt_propagate_n(h, mode: int, n_active: int):
+    _check(load().jt_propagate_n(h, int(mode), int(n_active)), "jt_propagate_n")
 
 
 def jt_marginal(h, slot: int, clique: int, out_ptr: Optional[int]) -> float:
@@ -268,8 +278,11 @@ class JunctionTree(JunctionTreePlan):
     def set_evidence(self, slot: int, vars: Sequence[int], states: Sequence[int]):
         jt_set_evidence(self.handle, slot, vars, states)
 
-    def propagate(self, mode: str = "fused"):
-        jt_propagate(self.handle, MODES[mode])
+    def propagate(self, mode: str = "fused", n_active: Optional[int] = None):
+        if n_active is None:
+            jt_propagate(self.handle, MODES[mode])
+        else:
+            jt_propagate_n(self.handle, MODES[mode], n_active)
 
     def profile(self, mode: str = "fused"):
         return jt_profile(self.handle, MODES[mode])

@@ -40,7 +40,7 @@ def compare(tree, plan, inst, slot, res, label=""):
     return worst
 
 
-def run_case(inst, modes=("fused", "graph", "plain"), slots=None, n_slots=None):
+def run_case(inst, modes=("fused", "graph", "plain", "dataflow"), slots=None, n_slots=None):
     jt = _gpu()
     plan = oracle.Plan.from_instance(inst)
     tree = jt.JunctionTree.from_instance(inst, n_slots=n_slots)
@@ -79,23 +79,23 @@ def test_c2_conditional_partition_function():
 
 
 def test_c3_full_size():
-    run_case(make_instance("c3", 0), modes=("fused", "plain"))
+    run_case(make_instance("c3", 0), modes=("fused", "plain", "dataflow"))
 
 
 def test_c3_other_seed_ragged():
-    run_case(make_instance("c3", 1, n_cliques=12), modes=("graph",))
+    run_case(make_instance("c3", 1, n_cliques=12), modes=("graph", "dataflow"))
 
 
 def test_c4_batched_slots():
     inst = make_instance("c4", 0, n_slots=8)
-    run_case(inst, modes=("fused", "graph"))
+    run_case(inst, modes=("fused", "graph", "dataflow"))
 
 
 def test_c4_full_batch_sampled():
     # the 256-slot batch in the launch configuration the benchmark times;
     # a sample of slots is checked against the oracle one by one
     inst = make_instance("c4", 0)
-    run_case(inst, modes=("graph",), slots=[0, 37, 128, 255])
+    run_case(inst, modes=("graph", "dataflow"), slots=[0, 37, 128, 255])
 
 
 def test_odd_shapes():
@@ -126,7 +126,7 @@ def test_zero_evidence():
     tree, plan, refs = run_case(inst)     # a zero separator entry: 0/0 rule, no NaN
     got, _ = tree.marginals_all(0)
     assert np.all(np.isfinite(got))
-    for mode in ("fused", "graph", "plain"):
+    for mode in ("fused", "graph", "plain", "dataflow"):
         tree.set_evidence(0, [1], [1])     # probability zero
         tree.propagate(mode)
         with pytest.raises(jt.JTError) as ei:
@@ -144,8 +144,11 @@ def test_determinism_and_idempotence():
     b, lb = tree.marginals_all(0)
     tree.propagate("graph")
     c, lc = tree.marginals_all(0)
+    tree.propagate("dataflow")
+    e, le = tree.marginals_all(0)
     assert np.array_equal(a, b) and la == lb
     assert np.array_equal(a, c) and la == lc
+    assert np.array_equal(a, e) and la == le
     # new evidence, then back: results follow the evidence, and come back bit-identical
     plan = oracle.Plan.from_instance(inst)
     tree.set_evidence(0, [3, 40], [1, 2])
