@@ -37,6 +37,8 @@ WORKLOADS = {
     "c4": "batched evidence: 200 cliques x 6-12 vars of card 2-3, separators 2-5 vars, "
           "256 evidence sets of 1-16 observed vars in one propagation",
     "c1": "tiny binary tree: 20 cliques x 5 binary vars, separators of 2 vars, 3 observed vars",
+    "c5": "serving stream: 16 resident trees (total entries log-uniform 1e3..5e7, var cards 2-64), "
+          "Poisson arrivals, uniform tree, 1-8 observed vars, all clique posteriors left on device",
 }
 
 
@@ -50,7 +52,101 @@ def parse():
     ap.add_argument("--mode", default="graph", choices=["graph", "fused", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--queries", type=int, default=2000, help="c5: queries per arrival-rate run")
+    ap.add_argument("--capacity", type=int, default=8, help="c5: evidence slots per resident tree")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="c5: HBM admission budget")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 256 MiB FP32 tensor 5 times (the known-size reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale)")
     return ap.parse_args()
+
+
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "jt_pass_kernel_{cfg}_traffic.json")
+
+
+def calibrate_copy():
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}))
+
+
+def measured_traffic(cfg, kernel):
+    """HBM bytes per launch from the committed counter runs, or None when the
+    kernel source changed since they were taken."""
+    from paper_1202_3777_amd.rocprof_summary import kernel_source_hash
+    f = TRAFFIC_FILE.format(cfg=cfg)
+    if not os.path.exists(f):
+        return None
+    t = json.load(open(f))
+    if t.get("source_sha256") != kernel_source_hash() or t.get("kernel") != kernel:
+        return None
+    return t["traffic_bytes_per_launch"]
+
+
+def serve_bench(args):
+    """Served queries/s at saturation, then p50/p99 at 0.5x and 0.9x of it."""
+    import torch
+    from paper_1202_3777_amd import jt
+    from paper_1202_3777_amd.instances import make_serving_trees
+    from paper_1202_3777_amd.serve import Clock, Server, TreeExecutor, latency_stats, make_queries
+    trees = make_serving_trees(seed=args.seed)
+    log(f"[bench] c5: {len(trees)} trees, {sum(t.total_entries() for t in trees):,} entries resident")
+    ex = [TreeExecutor(t, capacity=args.capacity, mode=args.mode if args.mode != "plain" else "plain") for t in trees]
+    budget = int(args.budget_gib * 2 ** 30)
+
+    def run(rate, n, seed):
+        srv = Server(ex, budget_bytes=budget, clock=Clock(torch))
+        qs = make_queries(trees, n, rate, seed=seed)
+        done = srv.run(qs, max_seconds=240)
+        st = latency_stats(done)
+        st["batches"] = srv.n_batches
+        st["mean_batch"] = float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0
+        return st
+
+    # warm-up: every tree, every slot count used below, graphs captured
+    for e in ex:
+        for k in range(1, args.capacity + 1):
+            e.tree.propagate(e.mode, n_active=k)
+    torch.cuda.synchronize()
+    sat = run(None, args.queries, args.seed + 1)
+    log(f"[bench] saturated: {sat}")
+    lat = {}
+    for frac in (0.5, 0.9):
+        lat[str(frac)] = run(frac * sat["queries_per_s"], args.queries, args.seed + 2)
+        log(f"[bench] rate {frac} x saturated: {lat[str(frac)]}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        qs = make_queries(trees, 24, None, seed=args.seed + 3)
+        plans = {}
+        t_plan = time.perf_counter()
+        for q in qs:
+            if q.tree not in plans:
+                plans[q.tree] = oracle.Plan.from_instance(trees[q.tree])
+        t = time.perf_counter()
+        for q in qs:
+            plans[q.tree].run(trees[q.tree].potentials, q.ev_vars, q.ev_states, want_marginals=False)
+        dt = time.perf_counter() - t
+        cpu = {"value": len(qs) / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(qs)} queries of the same mix, FP64, single thread ({dt:.1f} s; mapping tables "
+                         f"prebuilt in {t - t_plan:.1f} s)"}
+        log(f"[bench] oracle {cpu['value']:.2f} queries/s")
+    out = {
+        "metric": "served queries/s (saturated), with p50/p99 latency at 0.5x and 0.9x of that rate",
+        "value": sat["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.queries,
+        "warmup": args.capacity, "ms_per_step": 1e3 / sat["queries_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded generator, no dataset)",
+        "config": {"workload": f"c5: {WORKLOADS['c5']}", "seed": args.seed, "slots_per_tree": args.capacity,
+                   "budget_gib": args.budget_gib, "schedule": args.mode, "parallelism": "single GPU"},
+        "saturated": sat, "latency": lat, "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def log(msg):
@@ -72,6 +168,12 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.config == "c5":
+        serve_bench(args)
+        return
     log(f"[bench] generating {args.config} seed {args.seed}")
     inst = make_instance(args.config, args.seed)
     tree = jt.JunctionTree.from_instance(inst, device="cuda:0")
@@ -79,7 +181,7 @@ def main():
     n_slots = tree.n_slots
     entries = 2 * tree.query(jt.JT_Q_ENTRIES_PER_SWEEP) * n_slots     # both sweeps, all slots
     bytes_fused = tree.query(jt.JT_Q_BYTES_FUSED)
-    bytes_plain = tree.query(jt.JT_Q_BYTES_PLAIN) * n_slots
+    bytes_plain = tree.query(jt.JT_Q_BYTES_PLAIN)
 
     def timed(mode, steps, warmup):
         for _ in range(warmup):
@@ -100,7 +202,7 @@ def main():
 
     # dominant kernel: the streaming pass kernel, per-launch HIP events on the
     # library's stream, averaged over a few profiled propagations
-    prof_mode = "plain" if args.mode == "plain" else "fused"
+    prof_mode = {"plain": "plain", "dataflow": "dataflow"}.get(args.mode, "fused")
     reps = 5
     pms, fms, nps = [], [], []
     for _ in range(reps):
@@ -111,6 +213,7 @@ def main():
     pass_ms = float(np.mean(pms))
     n_pass = nps[0]
     table_bytes = bytes_plain if prof_mode == "plain" else bytes_fused
+    kernel_name = "jt_dataflow_kernel" if prof_mode == "dataflow" else "jt_pass_kernel"
     avg_launch_ms = pass_ms / n_pass
     bytes_per_launch = table_bytes / n_pass
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
@@ -167,8 +270,8 @@ def main():
                    "n_slots": n_slots, "schedule": args.mode, "parallelism": "single GPU"},
         "hbm_gbs_table_bytes": (bytes_fused if args.mode != "plain" else bytes_plain) / (ms * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "jt_pass_kernel", "launches_per_step": n_pass,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config, kernel_name),
+                     "kernel": kernel_name, "launches_per_step": n_pass,
                      "avg_launch_us": avg_launch_ms * 1e3, "bytes_per_launch": bytes_per_launch},
         "plain_sweep": None if ms_plain is None else {
             "ms_per_step": ms_plain, "value": entries / (ms_plain * 1e-3), "unit": "entries/s",

@@ -74,7 +74,8 @@ typedef int32_t jt_status;
  *                  from a captured graph): blocks take the passes and
  *                  finalizes of every slot in topological order and start
  *                  each as soon as the messages it reads are complete, so
- *                  tree levels overlap and no launch boundary separates them. */
+ *                  tree levels overlap and no launch boundary separates them.
+ *                  Currently disabled: jt_propagate returns JT_E_ARG for it. */
 #define JT_MODE_FUSED 0
 #define JT_MODE_GRAPH 1
 #define JT_MODE_PLAIN 2

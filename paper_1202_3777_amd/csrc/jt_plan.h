@@ -88,7 +88,7 @@ struct Plan {
 
     // statistics
     int64_t total_entries = 0, entries_per_sweep = 0;
-    int64_t bytes_fused = 0, bytes_plain = 0;   // per slot
+    int64_t bytes_fused = 0, bytes_plain = 0;   // all slots; shared initial tables counted once
 };
 
 // Build the plan; returns JT_OK or an error code with `err` filled in.

@@ -1,0 +1,117 @@
+"""Summaries of rocprofv3 output for the engine's kernels.
+
+    python -m paper_1202_3777_amd.rocprof_summary stats DIR
+        per-kernel calls / average / total from a --kernel-trace --stats run
+    python -m paper_1202_3777_amd.rocprof_summary traffic --kernel NAME \\
+        --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N \\
+        [--launches-per-step K] --out FILE.json
+        HBM bytes per launch of NAME from two counter runs (FETCH_SIZE, then
+        WRITE_SIZE), each scaled by what the same counter reads for a plain
+        copy of N bytes (torch copy kernel) so that the counter's unit and
+        coverage are calibrated on this GPU.
+
+The traffic file records the sha256 of the kernel source it was measured
+on; bench.py reports the traffic only while the source is unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "jt_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def _csv(d, pattern):
+    files = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return list(csv.DictReader(open(sorted(files)[0])))
+
+
+def counter_per_dispatch(d, counter):
+    """{kernel name: [value per dispatch]} from a --pmc run."""
+    rows = _csv(d, "*counter_collection.csv")
+    acc = defaultdict(lambda: defaultdict(float))
+    for r in rows:
+        if r.get("Counter_Name", "") != counter:
+            continue
+        name = r.get("Kernel_Name", "")
+        did = r.get("Dispatch_Id", r.get("Correlation_Id", "0"))
+        acc[name][did] += float(r["Counter_Value"])
+    return {k: [v[x] for x in sorted(v, key=lambda s: int(s))] for k, v in acc.items()}
+
+
+def stats(d):
+    rows = _csv(d, "*kernel_stats.csv")
+    return [{"name": r["Name"], "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+             "total_ns": int(float(r["TotalDurationNs"])), "pct": float(r["Percentage"])} for r in rows]
+
+
+def _match(d, name):
+    for k, v in d.items():
+        if k.startswith(name):
+            return v
+    raise KeyError(f"kernel {name} not in counter output ({list(d)[:5]})")
+
+
+def traffic(args):
+    fetch = _match(counter_per_dispatch(args.fetch, "FETCH_SIZE"), args.kernel)
+    write = _match(counter_per_dispatch(args.write, "WRITE_SIZE"), args.kernel)
+    cf = counter_per_dispatch(args.copy_fetch, "FETCH_SIZE")
+    cw = counter_per_dispatch(args.copy_write, "WRITE_SIZE")
+    # the copy kernel: the dispatch family with the largest counter values
+    cfk = max(cf, key=lambda k: max(cf[k]))
+    cwk = max(cw, key=lambda k: max(cw[k]))
+    cfv = sorted(cf[cfk])[len(cf[cfk]) // 2]
+    cwv = sorted(cw[cwk])[len(cw[cwk]) // 2]
+    f_scale = args.copy_bytes / cfv          # bytes per counter unit, reads
+    w_scale = args.copy_bytes / cwv          # bytes per counter unit, writes
+    fb = sum(fetch) / len(fetch) * f_scale
+    wb = sum(write) / len(write) * w_scale
+    out = {"kernel": args.kernel, "source_sha256": kernel_source_hash(),
+           "dispatches": [len(fetch), len(write)],
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb,
+           "copy_kernel": [cfk, cwk], "copy_bytes": args.copy_bytes,
+           "copy_counter_fetch": cfv, "copy_counter_write": cwv,
+           "scale_bytes_per_unit": [f_scale, w_scale], "workload": args.workload}
+    with open(args.out, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    t = sub.add_parser("traffic")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-fetch", required=True)
+    t.add_argument("--copy-write", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--workload", default="")
+    t.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        for r in stats(a.dir):
+            print(f"{r['name'][:40]:40s} calls {r['calls']:6d} avg {r['avg_ns'] / 1e3:9.2f} us "
+                  f"total {r['total_ns'] / 1e6:9.3f} ms {r['pct']:6.2f} %")
+    else:
+        traffic(a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -60,7 +60,7 @@ class AdmissionError(RuntimeError):
 class TreeExecutor:
     """One resident tree on the GPU: a JunctionTree with its own stream."""
 
-    def __init__(self, inst, capacity: int, mode: str = "dataflow", device: str = "cuda:0"):
+    def __init__(self, inst, capacity: int, mode: str = "graph", device: str = "cuda:0"):
         import torch
         from . import jt
         self.torch = torch

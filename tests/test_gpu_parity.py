@@ -40,7 +40,7 @@ def compare(tree, plan, inst, slot, res, label=""):
     return worst
 
 
-def run_case(inst, modes=("fused", "graph", "plain", "dataflow"), slots=None, n_slots=None):
+def run_case(inst, modes=("fused", "graph", "plain"), slots=None, n_slots=None):
     jt = _gpu()
     plan = oracle.Plan.from_instance(inst)
     tree = jt.JunctionTree.from_instance(inst, n_slots=n_slots)
@@ -79,23 +79,23 @@ def test_c2_conditional_partition_function():
 
 
 def test_c3_full_size():
-    run_case(make_instance("c3", 0), modes=("fused", "plain", "dataflow"))
+    run_case(make_instance("c3", 0), modes=("fused", "plain"))
 
 
 def test_c3_other_seed_ragged():
-    run_case(make_instance("c3", 1, n_cliques=12), modes=("graph", "dataflow"))
+    run_case(make_instance("c3", 1, n_cliques=12), modes=("graph",))
 
 
 def test_c4_batched_slots():
     inst = make_instance("c4", 0, n_slots=8)
-    run_case(inst, modes=("fused", "graph", "dataflow"))
+    run_case(inst, modes=("fused", "graph"))
 
 
 def test_c4_full_batch_sampled():
     # the 256-slot batch in the launch configuration the benchmark times;
     # a sample of slots is checked against the oracle one by one
     inst = make_instance("c4", 0)
-    run_case(inst, modes=("graph", "dataflow"), slots=[0, 37, 128, 255])
+    run_case(inst, modes=("graph",), slots=[0, 37, 128, 255])
 
 
 def test_odd_shapes():
@@ -126,7 +126,7 @@ def test_zero_evidence():
     tree, plan, refs = run_case(inst)     # a zero separator entry: 0/0 rule, no NaN
     got, _ = tree.marginals_all(0)
     assert np.all(np.isfinite(got))
-    for mode in ("fused", "graph", "plain", "dataflow"):
+    for mode in ("fused", "graph", "plain"):
         tree.set_evidence(0, [1], [1])     # probability zero
         tree.propagate(mode)
         with pytest.raises(jt.JTError) as ei:
@@ -144,11 +144,8 @@ def test_determinism_and_idempotence():
     b, lb = tree.marginals_all(0)
     tree.propagate("graph")
     c, lc = tree.marginals_all(0)
-    tree.propagate("dataflow")
-    e, le = tree.marginals_all(0)
     assert np.array_equal(a, b) and la == lb
     assert np.array_equal(a, c) and la == lc
-    assert np.array_equal(a, e) and la == le
     # new evidence, then back: results follow the evidence, and come back bit-identical
     plan = oracle.Plan.from_instance(inst)
     tree.set_evidence(0, [3, 40], [1, 2])
@@ -182,3 +179,33 @@ def test_profile_reports_launches():
     assert npass > 0 and nfin > 0 and pm > 0 and fm > 0
     plan = oracle.Plan.from_instance(inst)
     compare(tree, plan, inst, 0, plan.run(inst.potentials, *inst.evidence[0]), "c1-profiled")
+
+
+DATAFLOW_SKIP = ("the persistent dataflow launch did not complete on its first GPU run (c1, seed 0); "
+                 "no cause has been shown, so the schedule is disabled and stays off the GPU until one is")
+
+
+@pytest.mark.skip(reason=DATAFLOW_SKIP)
+def test_dataflow_schedule_parity():
+    for inst in (make_instance("c1", 0), make_instance("c3", 1, n_cliques=12), make_instance("c4", 0, n_slots=8)):
+        run_case(inst, modes=("dataflow",))
+
+
+@pytest.mark.skip(reason=DATAFLOW_SKIP)
+def test_dataflow_bit_identical_to_levels():
+    jt = _gpu()
+    inst = make_instance("c2", 1, n_cliques=10)
+    tree = jt.JunctionTree.from_instance(inst)
+    tree.propagate("graph")
+    a, la = tree.marginals_all(0)
+    tree.propagate("dataflow")
+    e, le = tree.marginals_all(0)
+    assert np.array_equal(a, e) and la == le
+
+
+def test_dataflow_is_refused():
+    jt = _gpu()
+    tree = jt.JunctionTree.from_instance(make_instance("c1", 0))
+    with pytest.raises(jt.JTError) as ei:
+        tree.propagate("dataflow")
+    assert ei.value.code == jt.JT_E_ARG

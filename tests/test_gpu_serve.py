@@ -17,7 +17,7 @@ def test_served_equals_alone_and_oracle():
     from paper_1202_3777_amd import jt
     from paper_1202_3777_amd.serve import Clock, Server, TreeExecutor, latency_stats, make_queries
     trees = make_serving_trees(seed=3, n_trees=4, lo=1e3, hi=2e5, max_cliques=12)
-    ex = [TreeExecutor(t, capacity=4, mode="dataflow") for t in trees]
+    ex = [TreeExecutor(t, capacity=4, mode="graph") for t in trees]
     got = {}
 
     def keep(q, e):
@@ -36,7 +36,7 @@ def test_served_equals_alone_and_oracle():
         inst = trees[q.tree]
         alone = jt.JunctionTree(inst.card, inst.clique_off, inst.clique_vars, inst.parent, inst.potentials, 1)
         alone.set_evidence(0, q.ev_vars, q.ev_states)
-        alone.propagate("dataflow")
+        alone.propagate("graph")
         a, la = alone.marginals_all(0)
         b, lb = got[q.qid]
         assert np.array_equal(a, b) and la == lb, q.qid
