@@ -70,9 +70,10 @@ def traffic(args):
     write = _match(counter_per_dispatch(args.write, "WRITE_SIZE"), args.kernel)
     cf = counter_per_dispatch(args.copy_fetch, "FETCH_SIZE")
     cw = counter_per_dispatch(args.copy_write, "WRITE_SIZE")
-    # the copy kernel: the dispatch family with the largest counter values
-    cfk = max(cf, key=lambda k: max(cf[k]))
-    cwk = max(cw, key=lambda k: max(cw[k]))
+    # the reference copy kernel (torch's device-to-device copy); other
+    # kernels in that run (e.g. the fill that initializes the source) are not it
+    cfk = next(k for k in cf if "copyBuffer" in k or "copy" in k.lower())
+    cwk = next(k for k in cw if "copyBuffer" in k or "copy" in k.lower())
     cfv = sorted(cf[cfk])[len(cf[cfk]) // 2]
     cwv = sorted(cw[cwk])[len(cw[cwk]) // 2]
     f_scale = args.copy_bytes / cfv          # bytes per counter unit, reads

@@ -209,3 +209,21 @@ def test_dataflow_is_refused():
     with pytest.raises(jt.JTError) as ei:
         tree.propagate("dataflow")
     assert ei.value.code == jt.JT_E_ARG
+
+
+def test_propagate_active_prefix():
+    jt = _gpu()
+    inst = make_instance("c4", 7, n_slots=4)
+    tree = jt.JunctionTree.from_instance(inst)
+    tree.propagate("graph")
+    full = [tree.marginals_all(s) for s in range(4)]
+    for mode in ("fused", "graph"):
+        tree.propagate(mode, n_active=2)
+        for s in range(2):
+            a, la = tree.marginals_all(s)
+            assert np.array_equal(a, full[s][0]) and la == full[s][1]
+        with pytest.raises(jt.JTError) as ei:
+            tree.marginals_all(2)
+        assert ei.value.code == jt.JT_E_STATE
+    with pytest.raises(jt.JTError):
+        tree.propagate("graph", n_active=5)
