@@ -245,6 +245,8 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     // resets its counter, so no clearing is needed between propagations
     if (e == hipSuccess)
         e = hipMemsetAsync(t->ws + P.off_fcnt, 0, (size_t)P.n_slots * P.fcnt_stride * sizeof(int32_t), s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(t->ws + P.off_icnt, 0, (size_t)P.n_slots * P.icnt_stride * sizeof(int32_t), s);
     // initial tables into the aligned layout, one copy per clique
     int64_t src_off = 0;
     for (int32_t c = 0; c < P.n_cliques && e == hipSuccess; ++c) {
@@ -273,6 +275,8 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     d.df = reinterpret_cast<int32_t *>(t->ws + P.off_df);
     d.df_err = d.df + 1;
     d.df_stride = P.df_stride;
+    d.icnt = reinterpret_cast<int32_t *>(t->ws + P.off_icnt);
+    d.icnt_stride = P.icnt_stride;
     d.n_items = P.n_fused_items;
     d.n_units = (int32_t)P.units.size();
     d.n_msgs = (int32_t)P.msgs.size();

@@ -72,7 +72,8 @@ typedef struct {
     int32_t o_n_rout, o_n_cls, o_m_in, o_ssize;
     // dataflow schedule: messages this pass needs finalized first, and the
     // number of tasks (blocks) that make up the pass
-    int32_t dep_base, n_dep, n_tasks, pad;
+    int32_t dep_base, n_dep, n_tasks;
+    int32_t msg;                // message this pass produces and finalizes, -1 none
 } JtItem;
 
 // A block's share of an item: groups [g0, g1), spread over the block's waves.
@@ -152,10 +153,11 @@ typedef struct {
     const int32_t *deps;           // message indices the items depend on
     int32_t *df;                   // [0] next unit; then per slot: item done counts, message done flags
     int32_t *df_err;               // set when a dependency wait gives up
+    int32_t *icnt;                 // per-slot arrival counters of the pass items
     const int32_t *ev_idx;
     const JtEv *ev_ent;
     int64_t coll_stride, out_stride, sep_stride, partial_stride;
     int64_t lam_stride, scale_stride, ev_idx_stride, ev_ent_stride;
-    int64_t fsig_stride, fcnt_stride, df_stride;
+    int64_t fsig_stride, fcnt_stride, df_stride, icnt_stride;
     int32_t n_cliques, n_items, n_units, n_msgs;
 } JtDev;

@@ -31,6 +31,12 @@
 
 namespace {
 
+// Wait until this wave's memory operations are acknowledged (vmcnt(0);
+// expcnt and lgkmcnt left open).  Partials are written with agent-coherent
+// stores, so once acknowledged any block of the chip reads them with
+// agent-coherent loads -- no L2 write-back or invalidate is needed.
+__device__ __forceinline__ void wait_vm_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -137,23 +143,22 @@ __device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, 
     const int32_t rout_off = it.o_rout_tile;
     float *part = partial + (int64_t)slot * st.partial + it.partial_off;
 
-    // issue the loads of up to JT_UNROLL tiles [t0, min(t0 + U, t1))
-    auto issue = [&](TileBatch<VEC> &B, int t0, int t1, int tile_k) {
+    // Tile metadata of up to 64 tiles is fetched lane-parallel once per chunk
+    // (tile offset, each gather's Jout, the outer-evidence verdict) and read
+    // back per tile with readlane, so the streaming loads never wait on a
+    // dependent scalar lookup.
+    // issue the loads of chunk tiles [u0, min(u0 + U, nt))
+    auto issue = [&](TileBatch<VEC> &B, int u0, int nt, int my_o, uint64_t zmask) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
-            const int t = t0 + u;
+            const int uu = u0 + u;
             B.o[u] = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) B.x[u][q] = 0.f;
-            if (t < t1) {
-                const int o = has_out ? tile_k + meta[rout_off + t] : t;
+            if (uu < nt) {
+                const int o = __builtin_amdgcn_readlane(my_o, uu);
                 B.o[u] = o;
-                bool zero = false;
-                for (int e = ev0; e < ev1; ++e) {
-                    const JtEv E = evs[e];
-                    if (E.outer && ((o / E.stride) % E.card) != E.digit) zero = true;
-                }
-                if (!zero) {
+                if (!((zmask >> uu) & 1ull)) {
                     const float *base = src + (int64_t)o * T;
                     if (VEC == 4) {
                         if (valid[0]) {
@@ -173,10 +178,11 @@ __device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, 
         }
     };
     // multiply in the gathers, mask, scale, store, accumulate
-    auto consume = [&](const TileBatch<VEC> &B, int t0, int t1, float (&acc)[4]) {
+    auto consume = [&](const TileBatch<VEC> &B, int u0, int nt, const int (&my_jo)[JT_NG_REG], float (&acc)[4]) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
-            if (t0 + u >= t1) break;
+            const int uu = u0 + u;
+            if (uu >= nt) break;
             const int o = B.o[u];
             float v[4];
 #pragma unroll
@@ -184,7 +190,7 @@ __device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, 
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) {
                 if (gg < ngr) {
-                    const int jo = meta[gr[gg].jout_off + o];
+                    const int jo = __builtin_amdgcn_readlane(my_jo[gg], uu);
                     if (gr[gg].in_lds) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) v[q] *= lds_ratio[gr[gg].off + jo + jin[gg][q]];
@@ -234,13 +240,28 @@ __device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, 
             q1 = min(q0 + it.tpg, it.n_tiles);
         }
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        // two batches of tiles in flight: load one while the other is consumed
-        issue(A, q0, q1, tile_k);
-        for (int qq = q0; qq < q1; qq += 2 * JT_UNROLL) {
-            if (qq + JT_UNROLL < q1) issue(B, qq + JT_UNROLL, q1, tile_k);
-            consume(A, qq, q1, acc);
-            if (qq + 2 * JT_UNROLL < q1) issue(A, qq + 2 * JT_UNROLL, q1, tile_k);
-            if (qq + JT_UNROLL < q1) consume(B, qq + JT_UNROLL, q1, acc);
+        for (int cb = q0; cb < q1; cb += JT_WAVE) {
+            const int nt = min(JT_WAVE, q1 - cb);
+            const bool live = lane < nt;
+            int my_o = 0;
+            if (live) my_o = has_out ? tile_k + meta[rout_off + cb + lane] : cb + lane;
+            bool my_zero = false;
+            for (int e = ev0; e < ev1; ++e) {
+                const JtEv E = evs[e];
+                if (E.outer && ((my_o / E.stride) % E.card) != E.digit) my_zero = true;
+            }
+            const uint64_t zmask = __ballot(live && my_zero);
+            int my_jo[JT_NG_REG];
+#pragma unroll
+            for (int gg = 0; gg < JT_NG_REG; ++gg) my_jo[gg] = (gg < ngr && live) ? meta[gr[gg].jout_off + my_o] : 0;
+            // two batches of tiles in flight: load one while the other is consumed
+            issue(A, 0, nt, my_o, zmask);
+            for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
+                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o, zmask);
+                consume(A, uq, nt, my_jo, acc);
+                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o, zmask);
+                if (uq + JT_UNROLL < nt) consume(B, uq + JT_UNROLL, nt, my_jo, acc);
+            }
         }
         if (!has_out) continue;
 
@@ -259,7 +280,7 @@ __device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, 
             for (int cls = lane; cls < n_cls; cls += JT_WAVE) {
                 float s = 0.f;
                 for (int n = 0; n < m_in; ++n) s += lds_red[perm[cls * m_in + n]];
-                pout[clsj[cls]] = s;
+                __hip_atomic_store(pout + clsj[cls], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         } else {
             int P = JT_WAVE / n_cls;
@@ -269,43 +290,12 @@ __device__ __forceinline__ void pass_body(const JtItem &it, const JtTask &task, 
             if (cls < n_cls)
                 for (int n = part_i; n < m_in; n += P) s += lds_red[perm[cls * m_in + n]];
             for (int off = P >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (cls < n_cls && part_i == 0) pout[clsj[cls]] = s;
+            if (cls < n_cls && part_i == 0) __hip_atomic_store(pout + clsj[cls], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
 
 }  // namespace
-
-// One launch = the passes of one tree level (or one message) for every slot.
-// Buffers are separate __restrict__ parameters so the compiler can prove the
-// metadata is never written by the kernel and read it through the scalar
-// unit (uniform loads that do not wait on the streaming vector loads).
-extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
-    const JtTask *__restrict__ tasks, const JtItem *__restrict__ items, const JtGather *__restrict__ gathers,
-    const int32_t *__restrict__ meta, const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
-    const float *__restrict__ init, float *__restrict__ coll, float *__restrict__ out,
-    const float *__restrict__ sep, const float *__restrict__ scale, float *__restrict__ partial, PassStrides st,
-    int task_begin, int n_tasks) {
-    __shared__ float lds_ratio[JT_LDS_RATIO_FLOATS];
-    __shared__ float lds_red[JT_WAVES_PER_BLOCK][JT_TILE_MAX];
-    const int slot = blockIdx.x / n_tasks;
-    const JtTask task = tasks[task_begin + (blockIdx.x - slot * n_tasks)];
-    const JtItem it = items[task.item];
-    // stage the ratio tables this pass multiplies in
-    const float *sep_slot = sep + (int64_t)slot * st.sep;
-    for (int g = 0; g < it.n_gather_lds; ++g) {
-        const JtGather G = gathers[it.gather_base + g];
-        for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = sep_slot[G.sep_off + j];
-    }
-    __syncthreads();
-    float *red = lds_red[threadIdx.x / JT_WAVE];
-    if (it.vec == 4)
-        pass_body<4>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st, lds_ratio,
-                     red);
-    else
-        pass_body<1>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st, lds_ratio,
-                     red);
-}
 
 // Finalize: each block sums the split partials of jc separator entries
 // (JT_BLOCK / jc split rows per column, fixed order), writes them, and adds a
@@ -329,76 +319,21 @@ struct FinPtrs {
     int32_t n_cliques;
 };
 
-__device__ bool finalize_block(const FinPtrs &F, const JtFTask &ft, int slot, float *red, double *dred, float *sh_f,
-                               int *sh_last) {
+// Given sigma (the sum of the new separator table), update the FP64
+// log-scales and turn the raw table into the collect table (rescaled to mean
+// one) or the distribute ratio new/old with 0/0 := 0.  All threads call it;
+// thread tid owns entries tid, tid + JT_BLOCK, ...
+__device__ void finish_message(const FinPtrs &F, const JtMsg &m, int slot, double sigma, float *sh_f) {
     const int tid = threadIdx.x;
-    const JtMsg m = F.msgs[ft.msg];
     const int nc = F.n_cliques;
-    const float *P = F.partial + (int64_t)slot * F.partial_stride + m.partial_off;
     float *sep = F.sep + (int64_t)slot * F.sep_stride;
     double *lam = F.lam + (int64_t)slot * F.lam_stride;
     float *scl = F.scale + (int64_t)slot * F.scale_stride;
-    double *fsig = F.fsig + (int64_t)slot * F.fsig_stride;
-    int32_t *fcnt = F.fcnt + (int64_t)slot * F.fcnt_stride;
-    const int ssize = m.ssize, nsplit = m.nsplit;
+    const int ssize = m.ssize;
     float *raw = nullptr;
     if (m.kind == JT_MSG_COLLECT) raw = sep + m.sepc_off;
     if (m.kind == JT_MSG_DIST || m.kind == JT_MSG_PLAIN) raw = sep + m.sepd_off;
-
-    const int jc = ft.jc, R = JT_BLOCK / jc;
-    const int jj = tid & (jc - 1), r = tid / jc;
-    const int j = ft.j0 + jj;
-    float s = 0.f;
-    if (j < ft.j1) {
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        int p = r;
-        for (; p + 3 * R < nsplit; p += 4 * R) {
-            a0 += P[(int64_t)p * ssize + j];
-            a1 += P[(int64_t)(p + R) * ssize + j];
-            a2 += P[(int64_t)(p + 2 * R) * ssize + j];
-            a3 += P[(int64_t)(p + 3 * R) * ssize + j];
-        }
-        for (; p < nsplit; p += R) a0 += P[(int64_t)p * ssize + j];
-        s = (a0 + a1) + (a2 + a3);
-    }
-    red[tid] = s;
-    __syncthreads();
-    for (int h = R >> 1; h > 0; h >>= 1) {
-        if (r < h) red[tid] += red[tid + h * jc];
-        __syncthreads();
-    }
-    double v = 0.0;
-    if (r == 0 && j < ft.j1) {
-        const float x = red[jj];
-        if (raw) raw[j] = x;
-        v = (double)x;
-    }
-    dred[tid] = v;
-    __syncthreads();
-    for (int h = JT_BLOCK >> 1; h > 0; h >>= 1) {
-        if (tid < h) dred[tid] += dred[tid + h];
-        __syncthreads();
-    }
-    if (ft.nb > 1) {
-        if (tid == 0) fsig[m.fbase + ft.b] = dred[0];
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            __threadfence();
-            *sh_last = (atomicAdd(&fcnt[ft.msg], 1) == ft.nb - 1);
-            __threadfence();
-        }
-        __syncthreads();
-        if (!*sh_last) return false;
-        __threadfence();
-    }
     if (tid == 0) {
-        double sigma = dred[0];
-        if (ft.nb > 1) {
-            sigma = 0.0;
-            for (int b = 0; b < ft.nb; ++b) sigma += fsig[m.fbase + b];
-            fcnt[ft.msg] = 0;    // ready for the next propagation
-        }
         const double ns = (double)ssize;
         double f = 0.0;
         switch (m.kind) {
@@ -483,6 +418,154 @@ __device__ bool finalize_block(const FinPtrs &F, const JtFTask &ft, int slot, fl
             oldc[jx] = nw;
         }
     }
+}
+
+// The whole finalize of one message in one block: sum the split partials of
+// every separator entry in a fixed order, sigma in a fixed order, then finish.
+// Entry j is summed by thread j % JT_BLOCK (all splits), or, for separators
+// of fewer than 64 entries, by JT_BLOCK / 64 threads over interleaved splits
+// and a fixed LDS tree.  red: JT_BLOCK floats, dred: JT_BLOCK doubles.
+__device__ __forceinline__ float ldp(const float *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void finalize_whole(const FinPtrs &F, int mi, int slot, float *red, double *dred, float *sh_f) {
+    const int tid = threadIdx.x;
+    const JtMsg m = F.msgs[mi];
+    const float *P = F.partial + (int64_t)slot * F.partial_stride + m.partial_off;
+    float *sep = F.sep + (int64_t)slot * F.sep_stride;
+    float *raw = nullptr;
+    if (m.kind == JT_MSG_COLLECT) raw = sep + m.sepc_off;
+    if (m.kind == JT_MSG_DIST || m.kind == JT_MSG_PLAIN) raw = sep + m.sepd_off;
+    const int ssize = m.ssize, nsplit = m.nsplit;
+    double local = 0.0;
+    if (ssize >= 64) {
+        for (int j = tid; j < ssize; j += JT_BLOCK) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+            int p = 0;
+            for (; p + 3 < nsplit; p += 4) {
+                a0 += ldp(P + (int64_t)p * ssize + j);
+                a1 += ldp(P + (int64_t)(p + 1) * ssize + j);
+                a2 += ldp(P + (int64_t)(p + 2) * ssize + j);
+                a3 += ldp(P + (int64_t)(p + 3) * ssize + j);
+            }
+            for (; p < nsplit; ++p) a0 += ldp(P + (int64_t)p * ssize + j);
+            const float v = (a0 + a1) + (a2 + a3);
+            if (raw) raw[j] = v;
+            local += (double)v;
+        }
+    } else {
+        int sp2 = 1;
+        while (sp2 < ssize) sp2 <<= 1;
+        const int R = JT_BLOCK / sp2;
+        const int jj = tid & (sp2 - 1), r = tid / sp2;
+        float s = 0.f;
+        if (jj < ssize) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+            int p = r;
+            for (; p + 3 * R < nsplit; p += 4 * R) {
+                a0 += ldp(P + (int64_t)p * ssize + jj);
+                a1 += ldp(P + (int64_t)(p + R) * ssize + jj);
+                a2 += ldp(P + (int64_t)(p + 2 * R) * ssize + jj);
+                a3 += ldp(P + (int64_t)(p + 3 * R) * ssize + jj);
+            }
+            for (; p < nsplit; p += R) a0 += ldp(P + (int64_t)p * ssize + jj);
+            s = (a0 + a1) + (a2 + a3);
+        }
+        red[tid] = s;
+        __syncthreads();
+        for (int h = R >> 1; h > 0; h >>= 1) {
+            if (r < h) red[tid] += red[tid + h * sp2];
+            __syncthreads();
+        }
+        if (r == 0 && jj < ssize) {
+            const float v = red[jj];
+            if (raw) raw[jj] = v;      // thread jj: the same thread rescales it
+            local = (double)v;
+        }
+    }
+    dred[tid] = local;
+    __syncthreads();
+    for (int h = JT_BLOCK >> 1; h > 0; h >>= 1) {
+        if (tid < h) dred[tid] += dred[tid + h];
+        __syncthreads();
+    }
+    const double sigma = dred[0];
+    __syncthreads();
+    finish_message(F, m, slot, sigma, sh_f);
+}
+
+__device__ bool finalize_block(const FinPtrs &F, const JtFTask &ft, int slot, float *red, double *dred, float *sh_f,
+                               int *sh_last) {
+    const int tid = threadIdx.x;
+    const JtMsg m = F.msgs[ft.msg];
+    const int nc = F.n_cliques;
+    const float *P = F.partial + (int64_t)slot * F.partial_stride + m.partial_off;
+    float *sep = F.sep + (int64_t)slot * F.sep_stride;
+    double *lam = F.lam + (int64_t)slot * F.lam_stride;
+    float *scl = F.scale + (int64_t)slot * F.scale_stride;
+    double *fsig = F.fsig + (int64_t)slot * F.fsig_stride;
+    int32_t *fcnt = F.fcnt + (int64_t)slot * F.fcnt_stride;
+    const int ssize = m.ssize, nsplit = m.nsplit;
+    float *raw = nullptr;
+    if (m.kind == JT_MSG_COLLECT) raw = sep + m.sepc_off;
+    if (m.kind == JT_MSG_DIST || m.kind == JT_MSG_PLAIN) raw = sep + m.sepd_off;
+
+    const int jc = ft.jc, R = JT_BLOCK / jc;
+    const int jj = tid & (jc - 1), r = tid / jc;
+    const int j = ft.j0 + jj;
+    float s = 0.f;
+    if (j < ft.j1) {
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        int p = r;
+        for (; p + 3 * R < nsplit; p += 4 * R) {
+            a0 += P[(int64_t)p * ssize + j];
+            a1 += P[(int64_t)(p + R) * ssize + j];
+            a2 += P[(int64_t)(p + 2 * R) * ssize + j];
+            a3 += P[(int64_t)(p + 3 * R) * ssize + j];
+        }
+        for (; p < nsplit; p += R) a0 += P[(int64_t)p * ssize + j];
+        s = (a0 + a1) + (a2 + a3);
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int h = R >> 1; h > 0; h >>= 1) {
+        if (r < h) red[tid] += red[tid + h * jc];
+        __syncthreads();
+    }
+    double v = 0.0;
+    if (r == 0 && j < ft.j1) {
+        const float x = red[jj];
+        if (raw) raw[j] = x;
+        v = (double)x;
+    }
+    dred[tid] = v;
+    __syncthreads();
+    for (int h = JT_BLOCK >> 1; h > 0; h >>= 1) {
+        if (tid < h) dred[tid] += dred[tid + h];
+        __syncthreads();
+    }
+    if (ft.nb > 1) {
+        if (tid == 0) fsig[m.fbase + ft.b] = dred[0];
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            *sh_last = (atomicAdd(&fcnt[ft.msg], 1) == ft.nb - 1);
+            __threadfence();
+        }
+        __syncthreads();
+        if (!*sh_last) return false;
+        __threadfence();
+    }
+    double sigma = dred[0];
+    if (ft.nb > 1) {
+        sigma = 0.0;
+        for (int b = 0; b < ft.nb; ++b) sigma += fsig[m.fbase + b];
+        __syncthreads();
+        if (tid == 0) fcnt[ft.msg] = 0;    // ready for the next propagation
+    }
+    finish_message(F, m, slot, sigma, sh_f);
     return true;
 }
 
@@ -508,6 +591,73 @@ __device__ __forceinline__ FinPtrs fin_ptrs(const JtDev &d) {
 }
 
 }  // namespace
+
+// One launch = the passes of one tree level (or one message) for every slot.
+// Buffers are separate __restrict__ parameters so the compiler can prove the
+// metadata is never written by the kernel and read it through the scalar
+// unit (uniform loads that do not wait on the streaming vector loads).
+//
+// A pass that sums into a separator also finalizes that message: every block
+// of the item counts its arrival after its partials are written, and the
+// block that arrives last sums all split partials (fixed order), forms
+// sigma, the log-scales and the new table or ratio.  No block ever waits for
+// another, and the next level's launch sees finished messages.
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
+    const JtTask *__restrict__ tasks, const JtItem *__restrict__ items, const JtGather *__restrict__ gathers,
+    const int32_t *__restrict__ meta, const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
+    const float *__restrict__ init, float *__restrict__ coll, float *__restrict__ out, float *__restrict__ sep,
+    float *__restrict__ scale, float *__restrict__ partial, const JtMsg *__restrict__ msgs,
+    const int32_t *__restrict__ child_edges, double *__restrict__ lam, int32_t *__restrict__ flag,
+    int32_t *__restrict__ icnt, PassStrides st, int64_t lam_stride, int64_t icnt_stride, int n_cliques,
+    int task_begin, int n_tasks) {
+    __shared__ __align__(16) float lds_ratio[JT_LDS_RATIO_FLOATS];   // also the finalize's double scratch
+    __shared__ float lds_red[JT_WAVES_PER_BLOCK][JT_TILE_MAX];
+    __shared__ float sh_f;
+    __shared__ int sh_last;
+    const int slot = blockIdx.x / n_tasks;
+    const JtTask task = tasks[task_begin + (blockIdx.x - slot * n_tasks)];
+    const JtItem it = items[task.item];
+    // stage the ratio tables this pass multiplies in
+    const float *sep_slot = sep + (int64_t)slot * st.sep;
+    for (int g = 0; g < it.n_gather_lds; ++g) {
+        const JtGather G = gathers[it.gather_base + g];
+        for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = sep_slot[G.sep_off + j];
+    }
+    __syncthreads();
+    float *red = lds_red[threadIdx.x / JT_WAVE];
+    if (it.vec == 4)
+        pass_body<4>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st, lds_ratio,
+                     red);
+    else
+        pass_body<1>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st, lds_ratio,
+                     red);
+    if (it.msg < 0) return;
+    int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
+    wait_vm_stores();   // this wave's partials are acknowledged
+    __syncthreads();
+    if (threadIdx.x == 0) sh_last = (atomicAdd(cnt, 1) == it.n_tasks - 1);
+    __syncthreads();
+    if (!sh_last) return;
+    FinPtrs F;
+    F.msgs = msgs;
+    F.child_edges = child_edges;
+    F.partial = partial;
+    F.sep = sep;
+    F.lam = lam;
+    F.scale = scale;
+    F.flag = flag;
+    F.fsig = nullptr;
+    F.fcnt = nullptr;
+    F.partial_stride = st.partial;
+    F.sep_stride = st.sep;
+    F.lam_stride = lam_stride;
+    F.scale_stride = st.scale;
+    F.fsig_stride = 0;
+    F.fcnt_stride = 0;
+    F.n_cliques = n_cliques;
+    finalize_whole(F, it.msg, slot, lds_red[0], reinterpret_cast<double *>(lds_ratio), &sh_f);
+    if (threadIdx.x == 0) *cnt = 0;    // ready for the next propagation
+}
 
 extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_finalize_kernel(JtDev d, int ftask_begin, int n_ftasks) {
     __shared__ float red[JT_BLOCK];
@@ -670,7 +820,8 @@ hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slo
     st.ev_ent = d.ev_ent_stride;
     hipLaunchKernelGGL(jt_pass_kernel, dim3((unsigned)n_tasks * (unsigned)n_slots), dim3(JT_BLOCK), 0, s, d.tasks,
                        d.items, d.gathers, d.meta, d.ev_idx, d.ev_ent, d.init, d.coll, d.out, d.sep, d.scale,
-                       d.partial, st, task_begin, n_tasks);
+                       d.partial, d.msgs, d.child_edges, d.lam, d.flag, d.icnt, st, d.lam_stride, d.icnt_stride,
+                       d.n_cliques, task_begin, n_tasks);
     return hipGetLastError();
 }
 

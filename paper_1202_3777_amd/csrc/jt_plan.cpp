@@ -18,7 +18,7 @@ namespace {
 
 constexpr int64_t kAlignFloats = 64;       // 256-byte alignment of every table
 constexpr int64_t kTargetBlocks = 1024;    // blocks per launch the grouping aims for
-constexpr int64_t kPartialMax = 65536;     // cap on split partial floats per message
+constexpr int64_t kPartialMax = 16384;     // cap on split partial floats per message
 constexpr int64_t kMaxMeta = int64_t(1) << 30;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -255,6 +255,7 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
     it.ev = (src_kind == JT_SRC_INIT) ? 1 : 0;
     it.out_view = out_view;
     it.partial_off = partial_off;
+    it.msg = -1;
     const int64_t tiles_per_group = std::max<int64_t>(1, group_entries / C.T);
     if (out_view >= 0) {
         const JtView &V = P.views[out_view];
@@ -408,6 +409,18 @@ bool verify_plan(const Plan &P, std::string &why) {
                 return bad("tile cover");
         }
     }
+    for (size_t ii = 0; ii < P.items.size(); ++ii) {
+        const JtItem &it = P.items[ii];
+        if (it.n_tasks < 1) return bad("item without tasks");
+        if (it.msg < -1 || it.msg >= (int32_t)P.msgs.size()) return bad("item message");
+        if ((it.msg >= 0) != (it.out_view >= 0)) return bad("item output without message");
+        if (it.msg >= 0) {
+            const JtMsg &m = P.msgs[it.msg];
+            if (m.item != (int32_t)ii || m.partial_off != it.partial_off || m.nsplit != it.nsplit ||
+                m.ssize != it.o_ssize)
+                return bad("item message fields");
+        }
+    }
     for (const JtTask &t : P.tasks) {
         if (t.item < 0 || t.item >= (int32_t)P.items.size()) return bad("task item");
         if (t.g0 < 0 || t.g1 > P.items[t.item].n_groups || t.g0 >= t.g1) return bad("task groups");
@@ -464,7 +477,7 @@ bool verify_plan(const Plan &P, std::string &why) {
             if (seen != P.items[m.item].n_tasks) return bad("message item tasks");
         }
     }
-    for (const std::vector<Launch> *L : {&P.fused, &P.plain})
+    for (const std::vector<Launch> *L : {&P.fused, &P.fused_split, &P.plain})
         for (const Launch &l : *L) {
             if (l.is_pass == 1 && (l.begin < 0 || l.begin + l.count > (int32_t)P.tasks.size())) return bad("launch tasks");
             if (l.is_pass == 0 && (l.begin < 0 || l.begin + l.count > (int32_t)P.ftasks.size())) return bad("launch ftasks");
@@ -664,6 +677,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             JtMsg m;
             std::memset(&m, 0, sizeof(m));
             m.item = it;
+            P.items[it].msg = m0 + (int32_t)level_msgs.size();
             m.kind = is_root ? JT_MSG_TOTAL : JT_MSG_COLLECT;
             m.edge = is_root ? -1 : c;
             m.from = c;
@@ -682,8 +696,9 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
         const int32_t f0 = (int32_t)P.ftasks.size();
         for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
+        P.fused_split.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        P.fused_split.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        P.fused.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
     }
     for (int32_t d = 0; d <= P.depth; ++d) {
         const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
@@ -724,6 +739,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                 JtMsg m;
                 std::memset(&m, 0, sizeof(m));
                 m.item = it;
+                P.items[it].msg = m0 + (int32_t)level_msgs.size();
                 m.kind = JT_MSG_DIST;
                 m.edge = ch;
                 m.from = c;
@@ -740,13 +756,14 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
         const int32_t f0 = (int32_t)P.ftasks.size();
         for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
+        P.fused_split.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        if (!level_msgs.empty()) P.fused_split.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        if (!level_msgs.empty()) P.fused.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
     }
     P.bytes_fused = bytes;
 
     // dataflow order: the fused launches' tasks and finalize tasks, in order
-    for (const Launch &l : P.fused)
+    for (const Launch &l : P.fused_split)
         for (int32_t x = l.begin; x < l.begin + l.count; ++x) P.units.push_back({l.is_pass ? 0 : 1, x});
     P.n_fused_items = (int32_t)P.items.size();
 
@@ -778,6 +795,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         JtMsg m;
         std::memset(&m, 0, sizeof(m));
         m.kind = JT_MSG_PLAIN;
+        m.item = it;
         m.edge = e;
         m.from = from;
         m.to = to;
@@ -787,9 +805,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         m.sepc_off = P.edge[e].sepc_off;
         m.sepd_off = P.edge[e].sepd_off;
         P.msgs.push_back(m);
-        const int32_t f0 = (int32_t)P.ftasks.size();
+        P.items[it].msg = (int32_t)P.msgs.size() - 1;
         add_ftasks(P, (int32_t)P.msgs.size() - 1, fsig_count);
-        P.plain.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         const int32_t t1 = (int32_t)P.tasks.size();
         const int32_t it2 = add_item(P, to, JT_SRC_OUT, P.cl[to].out_off, JT_DST_OUT, P.cl[to].out_off, {{e, true}},
                                      -1, -1, 0, bytes, group_entries_for(P.cl[to].size));
@@ -844,13 +861,13 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             m.ssize = 1;
             m.nsplit = P.items[it].nsplit;
             m.partial_off = poff;
+            m.item = it;
             P.msgs.push_back(m);
+            P.items[it].msg = (int32_t)P.msgs.size() - 1;
         }
-        const int32_t f0 = (int32_t)P.ftasks.size();
         for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
         emit_tasks(P, i0, (int32_t)P.items.size());
         P.plain.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        P.plain.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         const int32_t t1 = (int32_t)P.tasks.size();
         const int32_t i1 = (int32_t)P.items.size();
         for (int32_t c = 0; c < nc; ++c)
@@ -912,6 +929,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_deps = region(std::max<size_t>(1, P.deps.size()) * sizeof(int32_t));
     P.df_stride = align_up((int64_t)P.n_fused_items + (int64_t)P.msgs.size(), kAlignFloats);
     P.off_df = region((size_t)(kAlignFloats + S * P.df_stride) * sizeof(int32_t));
+    P.icnt_stride = align_up(std::max<int64_t>(1, (int64_t)P.items.size()), kAlignFloats);
+    P.off_icnt = region(S * (size_t)P.icnt_stride * sizeof(int32_t));
     P.off_fsig = region(S * (size_t)P.fsig_stride * sizeof(double));
     P.off_fcnt = region(S * (size_t)P.fcnt_stride * sizeof(int32_t));
     P.total_bytes = off;
@@ -920,7 +939,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                    (size_t)P.lam_stride * sizeof(double) + (size_t)P.scale_stride * sizeof(float) + sizeof(int32_t) +
                    (size_t)P.ev_idx_stride * sizeof(int32_t) + (size_t)P.ev_ent_stride * sizeof(JtEv) +
                    (size_t)P.fsig_stride * sizeof(double) + (size_t)P.fcnt_stride * sizeof(int32_t) +
-                   (size_t)P.df_stride * sizeof(int32_t);
+                   (size_t)P.df_stride * sizeof(int32_t) + (size_t)P.icnt_stride * sizeof(int32_t);
     std::string why;
     if (!verify_plan(P, why)) return fail(err, JT_E_ARG, why);
     return JT_OK;

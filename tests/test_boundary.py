@@ -163,4 +163,8 @@ def test_schedule_facts(name, kw):
     exp_p += sum(12 * int(s) for s in sizes)
     assert plan.query(jt.JT_Q_BYTES_PLAIN) == exp_p
     n = inst.n_cliques
-    assert plan.query(jt.JT_Q_N_LAUNCHES_PLAIN) == 2 + 3 * 2 * (n - 1) + 3
+    # set-up kernel + reset pass, (marginalize-and-finalize, scatter) per
+    # message, totals-and-finalize + normalize at the end
+    assert plan.query(jt.JT_Q_N_LAUNCHES_PLAIN) == 2 + 2 * 2 * (n - 1) + 2
+    # one pass launch per collect level and per distribute level
+    assert plan.query(jt.JT_Q_N_LAUNCHES_FUSED) == plan.query(jt.JT_Q_HEIGHT) + plan.query(jt.JT_Q_DEPTH)
