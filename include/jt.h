@@ -70,12 +70,11 @@ typedef int32_t jt_status;
  *   JT_MODE_PLAIN  one message at a time in the paper's depth-first order
  *                  (Algorithms 2-3): marginalize, ratio, scatter launches per
  *                  message, tables updated in place;
- *   JT_MODE_DATAFLOW  the fused passes as one persistent launch (replayed
- *                  from a captured graph): blocks take the passes and
- *                  finalizes of every slot in topological order and start
- *                  each as soon as the messages it reads are complete, so
- *                  tree levels overlap and no launch boundary separates them.
- *                  Currently disabled: jt_propagate returns JT_E_ARG for it. */
+ *   JT_MODE_DATAFLOW  reserved for a persistent schedule that overlaps tree
+ *                  levels; disabled: jt_propagate and jt_profile return
+ *                  JT_E_ARG for it.
+ * In every schedule a message is finalized (new separator table, rescale,
+ * ratio, log-scales) inside the pass launch that produces it. */
 #define JT_MODE_FUSED 0
 #define JT_MODE_GRAPH 1
 #define JT_MODE_PLAIN 2
@@ -178,9 +177,10 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *   JT_Q_N_LAUNCHES_FUSED, JT_Q_N_LAUNCHES_PLAIN (kernel launches per
  *     propagation), JT_Q_HEIGHT (levels of the collect sweep),
  *   JT_Q_DEPTH (levels of the distribute sweep),
- *   JT_Q_FUSED_LAUNCH_KIND (arg = launch index: 1 pass, 0 finalize),
- *   JT_Q_FUSED_LAUNCH_BYTES (arg = launch index: FP32 table bytes of a
- *     pass launch, 0 for a finalize),
+ *   JT_Q_FUSED_LAUNCH_KIND (arg = launch index: 1, a pass launch -- every
+ *     launch of the fused schedule is one),
+ *   JT_Q_FUSED_LAUNCH_BYTES (arg = launch index: FP32 table bytes of that
+ *     pass launch),
  *   JT_Q_SLOT_BYTES (workspace bytes each slot adds),
  *   JT_Q_SHARED_BYTES (workspace bytes independent of the slot count).
  * Errors: JT_E_ARG. */
@@ -202,12 +202,14 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and
- * report the device time spent in the streaming pass launches and in the
- * finalize launches (milliseconds, summed over the propagation) and how many
+ * report the device time spent in the pass launches (which finalize their
+ * messages too) and in the other launches -- the set-up kernel of
+ * JT_MODE_PLAIN -- (milliseconds, summed over the propagation) and how many
  * of each ran.  Synchronizes the bound stream.  For measurement only; the
  * results it leaves are those of a normal jt_propagate.
  *   mode  JT_MODE_FUSED or JT_MODE_PLAIN;
- *   pass_ms, finalize_ms, n_pass, n_finalize  host pointers (any may be NULL).
+ *   pass_ms, finalize_ms, n_pass, n_finalize  host pointers (any may be NULL);
+ *     finalize_ms and n_finalize count the launches other than passes.
  * Errors: JT_E_STATE, JT_E_ARG, JT_E_HIP. */
 jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_ms, int32_t *n_pass,
                      int32_t *n_finalize);

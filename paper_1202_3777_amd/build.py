@@ -35,25 +35,28 @@ def sources():
         os.path.join(ROOT, "include", "jt.h")]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD) -> str:
+    """Compile and link the library; ``defines`` are extra -D flags for both
+    compilers (tuning constants), ``out`` the library path."""
+    os.makedirs(build_dir, exist_ok=True)
+    dfl = [f"-D{d}" for d in defines]
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     objs = []
     for s in HOST_SRCS:
-        o = os.path.join(BUILD, s.replace(".cpp", ".o"))
+        o = os.path.join(build_dir, s.replace(".cpp", ".o"))
         _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
-              "-I", os.path.join(ROCM, "include")] + inc + ["-c", os.path.join(CSRC, s), "-o", o])
+              "-I", os.path.join(ROCM, "include")] + dfl + inc + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     for s in DEVICE_SRCS:
-        o = os.path.join(BUILD, s.replace(".hip", ".o"))
-        _run([HIPCC] + DEVICE_FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", o])
+        o = os.path.join(build_dir, s.replace(".hip", ".o"))
+        _run([HIPCC] + DEVICE_FLAGS + dfl + inc + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -14,11 +14,8 @@
 #include "jt.h"
 #include "jt_plan.h"
 
-hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, hipStream_t s);
-hipError_t jt_launch_finalize(const JtDev &d, int msg_begin, int n_msgs, int n_slots, hipStream_t s);
+hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, int lds_floats, hipStream_t s);
 hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s);
-hipError_t jt_launch_dataflow(const JtDev &d, int n_slots, int grid, hipStream_t s);
-int jt_dataflow_blocks_per_cu();
 
 namespace {
 
@@ -47,21 +44,20 @@ struct jt_tree_s {
     std::vector<char> ev_dirty;
     std::vector<int32_t> ev_idx_host;   // [n_slots][ev_idx_stride]
     std::vector<JtEv> ev_ent_host;      // [n_slots][ev_ent_stride]
-    // captured graphs keyed by (schedule, active slots): 0 level launches, 1 dataflow
-    std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
-    int df_blocks = 1;    // resident blocks of the persistent kernel
+    // captured graphs of the level launches, keyed by the number of active slots
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     int last_mode = -1;
     int last_n_active = 0;
 };
 
 namespace {
 
-// The persistent dataflow launch is switched off: its first run on the GPU
-// did not complete, and no cause has been shown yet.  The kernel stays in the
-// source; the schedule is refused until it is fixed.
+// The persistent dataflow schedule is switched off: its first run on the GPU
+// did not complete and no cause was shown, so its kernel was taken out and
+// the mode is refused.
 jt_status dataflow_disabled() {
-    return set_err(JT_E_ARG, "the dataflow schedule is disabled in this build (its launch did not complete on "
-                             "the GPU; cause not yet found)");
+    return set_err(JT_E_ARG, "the dataflow schedule is disabled (its launch did not complete on the GPU; "
+                             "cause not found)");
 }
 
 jt_status check_tree(jt_tree t) {
@@ -101,8 +97,7 @@ jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L, int S) {
             e = jt_launch_plain_init(t->dev, S, t->stream);
         } else if (l.count > 0) {
             if ((int64_t)l.count * S > 0x7fffffffLL) return set_err(JT_E_TOO_LARGE, "grid too large");
-            e = l.is_pass ? jt_launch_pass(t->dev, l.begin, l.count, S, t->stream)
-                          : jt_launch_finalize(t->dev, l.begin, l.count, S, t->stream);
+            e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, t->stream);
         }
         if (e != hipSuccess) return hip_err(e, "kernel launch");
     }
@@ -117,23 +112,14 @@ void drop_graph(jt_tree t) {
     t->graphs.clear();
 }
 
-jt_status enqueue_dataflow(jt_tree t, int S) {
-    const int64_t units = std::max<int64_t>(1, (int64_t)t->plan.units.size() * S);
-    const int grid = (int)std::min<int64_t>(t->df_blocks, units);
-    hipError_t e = jt_launch_dataflow(t->dev, S, grid, t->stream);
-    if (e != hipSuccess) return hip_err(e, "dataflow launch");
-    return JT_OK;
-}
-
-// Capture the launches of one propagation once per (schedule, active
-// slots), then replay the graph.
-jt_status run_graph(jt_tree t, int k, int S) {
-    auto key = std::make_pair(k, S);
-    auto f = t->graphs.find(key);
+// Capture the launches of one propagation once per number of active slots,
+// then replay the graph.
+jt_status run_graph(jt_tree t, int S) {
+    auto f = t->graphs.find(S);
     if (f == t->graphs.end()) {
         hipError_t e = hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_err(e, "begin capture");
-        jt_status rc = k == 0 ? enqueue(t, t->plan.fused, S) : enqueue_dataflow(t, S);
+        jt_status rc = enqueue(t, t->plan.fused, S);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(t->stream, &g);
         if (rc != JT_OK) {
@@ -147,7 +133,7 @@ jt_status run_graph(jt_tree t, int k, int S) {
             (void)hipGraphDestroy(g);
             return hip_err(e, "graph instantiate");
         }
-        f = t->graphs.emplace(key, std::make_pair(g, x)).first;
+        f = t->graphs.emplace(S, std::make_pair(g, x)).first;
     }
     hipError_t e = hipGraphLaunch(f->second.second, t->stream);
     if (e != hipSuccess) return hip_err(e, "graph launch");
@@ -170,12 +156,6 @@ jt_status read_slot(jt_tree t, int32_t slot, double *log_z, bool *zero) {
     e = hipMemcpy(&lz, t->ws + P.off_lam + ((size_t)slot * P.lam_stride + JT_LAM_LOGZ(P.n_cliques)) * sizeof(double),
                   sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_err(e, "read log Z");
-    if (t->last_mode == JT_MODE_DATAFLOW) {
-        int32_t derr = 0;
-        e = hipMemcpy(&derr, t->ws + P.off_df + sizeof(int32_t), sizeof(int32_t), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_err(e, "read dataflow status");
-        if (derr) return set_err(JT_E_HIP, "dataflow dependency wait timed out; results are invalid");
-    }
     *zero = flag != 0;
     if (log_z) *log_z = *zero ? -INFINITY : lz;
     return JT_OK;
@@ -238,13 +218,8 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     if (e == hipSuccess) e = up(P.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(JtTask));
     if (e == hipSuccess) e = up(P.off_msgs, P.msgs.data(), P.msgs.size() * sizeof(JtMsg));
     if (e == hipSuccess) e = up(P.off_child, P.child_edges.data(), P.child_edges.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = up(P.off_ftasks, P.ftasks.data(), P.ftasks.size() * sizeof(JtFTask));
-    if (e == hipSuccess) e = up(P.off_units, P.units.data(), P.units.size() * sizeof(JtUnit));
-    if (e == hipSuccess) e = up(P.off_deps, P.deps.data(), P.deps.size() * sizeof(int32_t));
-    // finalize arrival counters start at zero; each finalize's last block
+    // pass arrival counters start at zero; the block that finalizes a message
     // resets its counter, so no clearing is needed between propagations
-    if (e == hipSuccess)
-        e = hipMemsetAsync(t->ws + P.off_fcnt, 0, (size_t)P.n_slots * P.fcnt_stride * sizeof(int32_t), s);
     if (e == hipSuccess)
         e = hipMemsetAsync(t->ws + P.off_icnt, 0, (size_t)P.n_slots * P.icnt_stride * sizeof(int32_t), s);
     // initial tables into the aligned layout, one copy per clique
@@ -265,28 +240,9 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     d.tasks = region<JtTask>(t, P.off_tasks);
     d.msgs = region<JtMsg>(t, P.off_msgs);
     d.child_edges = region<int32_t>(t, P.off_child);
-    d.ftasks = region<JtFTask>(t, P.off_ftasks);
-    d.fsig = reinterpret_cast<double *>(t->ws + P.off_fsig);
-    d.fcnt = reinterpret_cast<int32_t *>(t->ws + P.off_fcnt);
-    d.fsig_stride = P.fsig_stride;
-    d.fcnt_stride = P.fcnt_stride;
-    d.units = region<JtUnit>(t, P.off_units);
-    d.deps = region<int32_t>(t, P.off_deps);
-    d.df = reinterpret_cast<int32_t *>(t->ws + P.off_df);
-    d.df_err = d.df + 1;
-    d.df_stride = P.df_stride;
     d.icnt = reinterpret_cast<int32_t *>(t->ws + P.off_icnt);
     d.icnt_stride = P.icnt_stride;
-    d.n_items = P.n_fused_items;
-    d.n_units = (int32_t)P.units.size();
     d.n_msgs = (int32_t)P.msgs.size();
-    {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 1;
-        t->df_blocks = cus * jt_dataflow_blocks_per_cu();
-    }
     d.init = region<float>(t, P.off_init);
     d.coll = reinterpret_cast<float *>(t->ws + P.off_coll);
     d.out = reinterpret_cast<float *>(t->ws + P.off_out);
@@ -346,7 +302,7 @@ jt_status jt_propagate_n(jt_tree t, int32_t mode, int32_t n_active) {
     else if (mode == JT_MODE_PLAIN)
         rc = enqueue(t, t->plan.plain, n_active);
     else
-        rc = run_graph(t, mode == JT_MODE_GRAPH ? 0 : 1, n_active);
+        rc = run_graph(t, n_active);
     if (rc == JT_OK) {
         t->propagated = true;
         t->last_mode = mode;
@@ -482,33 +438,6 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
         return set_err(JT_E_ARG, "profile mode must be fused, plain or dataflow");
     if (jt_status rc = upload_evidence(t)) return rc;
     if (mode == JT_MODE_DATAFLOW) return dataflow_disabled();
-    if (mode == JT_MODE_DATAFLOW) {
-        // the persistent launch is the pass; its counter reset is reported
-        // as the finalize share
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
-        if (e == hipSuccess) e = hipEventRecord(ev[0], t->stream);
-        if (e == hipSuccess) {
-            const int64_t units = std::max<int64_t>(1, (int64_t)t->plan.units.size() * t->plan.n_slots);
-            e = jt_launch_dataflow(t->dev, t->plan.n_slots, (int)std::min<int64_t>(t->df_blocks, units), t->stream);
-        }
-        if (e == hipSuccess) e = hipEventRecord(ev[2], t->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[2]);
-        for (int k = 0; k < 3; ++k)
-            if (ev[k]) (void)hipEventDestroy(ev[k]);
-        if (e != hipSuccess) return hip_err(e, "profiled dataflow launch");
-        t->propagated = true;
-        t->last_mode = mode;
-        t->last_n_active = t->plan.n_slots;
-        if (pass_ms) *pass_ms = ms;
-        if (finalize_ms) *finalize_ms = 0.0;
-        if (n_pass) *n_pass = 1;
-        if (n_finalize) *n_finalize = 0;
-        return JT_OK;
-    }
     const std::vector<jt::Launch> &L = mode == JT_MODE_FUSED ? t->plan.fused : t->plan.plain;
     const int S = t->plan.n_slots;
     t->last_n_active = S;
@@ -534,8 +463,7 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
             if (l.is_pass == 2)
                 e = jt_launch_plain_init(t->dev, S, t->stream);
             else
-                e = l.is_pass ? jt_launch_pass(t->dev, l.begin, l.count, S, t->stream)
-                              : jt_launch_finalize(t->dev, l.begin, l.count, S, t->stream);
+                e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, t->stream);
         }
         if (e == hipSuccess) e = hipEventRecord(b, t->stream);
         if (e != hipSuccess) {
@@ -559,7 +487,7 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
         if (kind[i] == 1) {
             tp += ms;
             ++np;
-        } else if (kind[i] == 0) {
+        } else {
             tf += ms;
             ++nf;
         }

@@ -21,8 +21,17 @@
 #define JT_WAVES_PER_BLOCK (JT_BLOCK / JT_WAVE)
 #define JT_TILE_MAX 256           /* one wave covers a tile: 64 lanes x 4 entries */
 #define JT_NG_REG 4               /* gathers whose Jin values live in registers */
-#define JT_LDS_RATIO_FLOATS 8192  /* 32 KiB of LDS for staged ratio tables */
-#define JT_UNROLL 4               /* tiles in flight per wave */
+#define JT_LDS_RATIO_FLOATS 8192  /* at most 32 KiB of LDS for staged ratio tables */
+#define JT_FIN_LDS_FLOATS 64      /* smallest dynamic LDS of a pass launch */
+#ifndef JT_FIN_BATCH
+#define JT_FIN_BATCH 16           /* partial loads a finalize thread issues before using them */
+#endif
+#ifndef JT_UNROLL
+#define JT_UNROLL 4               /* tiles per batch; two batches in flight per wave */
+#endif
+#ifndef JT_WAVE_GROUP_TILES
+#define JT_WAVE_GROUP_TILES 16    /* output views with at most this many tiles per kept-outer configuration use wave groups */
+#endif
 
 // One clique table seen through one separator (or through the empty
 // separator, for the table's total).
@@ -62,21 +71,23 @@ typedef struct {
     int32_t scale_clique;       // -1: no scaling
     int32_t ev;                 // 1: enter this slot's evidence of `clique`
     int32_t out_view;           // -1: no reduction output
-    int32_t tpg;                // tiles per group
+    int32_t tpg;                // tiles per group (a group is streamed by one block, its
+                                // tiles shared out over the block's waves)
     int32_t nsplit;             // groups per kept-outer configuration
-    int32_t n_groups;
+    int32_t n_groups;           // per slot; one partial row of the output view per group
     int64_t partial_off;        // float offset in the per-slot partial region
     // the output view's reduction tables, copied here to keep the kernel
     // prologue short (meta offsets stay below 2^30)
     int32_t o_kout_tile, o_kout_j, o_rout_tile, o_perm, o_clsj;
     int32_t o_n_rout, o_n_cls, o_m_in, o_ssize;
-    // dataflow schedule: messages this pass needs finalized first, and the
-    // number of tasks (blocks) that make up the pass
-    int32_t dep_base, n_dep, n_tasks;
+    int32_t n_tasks;            // blocks per slot that make up the pass
     int32_t msg;                // message this pass produces and finalizes, -1 none
+    int32_t wave_groups;        // 1: short groups (one kept-outer configuration each,
+                                // all its tiles), each streamed whole by one wave
+    int32_t pad;
 } JtItem;
 
-// A block's share of an item: groups [g0, g1), spread over the block's waves.
+// A block's share of an item: groups [g0, g1), one after the other.
 typedef struct {
     int32_t item, g0, g1, pad;
 } JtTask;
@@ -99,21 +110,8 @@ typedef struct {
     int64_t partial_off;
     int32_t child_base, n_children;  // children edges of `from` (collect log-scale sum)
     int32_t sepc_off, sepd_off;      // separator tables in the per-slot region
-    int32_t fbase, nfb;              // finalize blocks: per-slot sigma scratch index, count
     int32_t item, pad;               // the pass item whose partials this message sums
 } JtMsg;
-
-// One unit of the dataflow schedule: a pass task or a finalize task.
-typedef struct {
-    int32_t kind;    // 0 = pass task, 1 = finalize task
-    int32_t index;   // into tasks or ftasks
-} JtUnit;
-
-// A block's share of one message's finalize: separator entries [j0, j1),
-// jc columns by JT_BLOCK / jc split rows; block b of nb for the message.
-typedef struct {
-    int32_t msg, j0, j1, jc, b, nb, pad0, pad1;
-} JtFTask;
 
 // One digit condition of hard evidence: entry kept iff
 // (index / stride) % card == digit, index being the tile index for outer
@@ -137,7 +135,6 @@ typedef struct {
     const JtItem *items;
     const JtTask *tasks;
     const JtMsg *msgs;
-    const JtFTask *ftasks;
     const int32_t *child_edges;
     const float *init;
     float *coll;
@@ -147,17 +144,11 @@ typedef struct {
     double *lam;
     float *scale;
     int32_t *flag;
-    double *fsig;                  // per-slot block sums of the finalize
-    int32_t *fcnt;                 // per-slot arrival counters, one per message
-    const JtUnit *units;           // dataflow schedule
-    const int32_t *deps;           // message indices the items depend on
-    int32_t *df;                   // [0] next unit; then per slot: item done counts, message done flags
-    int32_t *df_err;               // set when a dependency wait gives up
     int32_t *icnt;                 // per-slot arrival counters of the pass items
     const int32_t *ev_idx;
     const JtEv *ev_ent;
     int64_t coll_stride, out_stride, sep_stride, partial_stride;
     int64_t lam_stride, scale_stride, ev_idx_stride, ev_ent_stride;
-    int64_t fsig_stride, fcnt_stride, df_stride, icnt_stride;
-    int32_t n_cliques, n_items, n_units, n_msgs;
+    int64_t icnt_stride;
+    int32_t n_cliques, n_msgs;
 } JtDev;

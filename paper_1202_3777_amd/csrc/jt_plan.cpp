@@ -17,8 +17,24 @@ namespace jt {
 namespace {
 
 constexpr int64_t kAlignFloats = 64;       // 256-byte alignment of every table
-constexpr int64_t kTargetBlocks = 1024;    // blocks per launch the grouping aims for
-constexpr int64_t kPartialMax = 16384;     // cap on split partial floats per message
+// Tuning constants (overridable at build time for sweeps).
+#ifndef JT_TARGET_BLOCKS
+#define JT_TARGET_BLOCKS 1024
+#endif
+#ifndef JT_PARTIAL_MAX
+#define JT_PARTIAL_MAX 16384
+#endif
+#ifndef JT_GROUP_MIN
+#define JT_GROUP_MIN 4096
+#endif
+#ifndef JT_GROUP_MAX
+#define JT_GROUP_MAX 32768
+#endif
+#ifndef JT_GROUP_DIV
+#define JT_GROUP_DIV 1024
+#endif
+constexpr int64_t kTargetBlocks = JT_TARGET_BLOCKS;   // blocks per launch the grouping aims for
+constexpr int64_t kPartialMax = JT_PARTIAL_MAX;       // cap on split partial floats per message
 constexpr int64_t kMaxMeta = int64_t(1) << 30;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -182,26 +198,30 @@ struct GatherSpec {
     bool dist;   // ratio of the distribute sweep (else the collect table)
 };
 
-// Append one pass item and the tasks that cover it.
-// Group size of a launch that streams `level_entries` table entries per
+// Entries of one group (the tiles one block streams and reduces to one
+// partial row) in a launch that streams `level_entries` table entries per
 // slot: small levels are cut finer (to spread over the chip), large ones
-// coarser (to amortize each wave's set-up and its in-tile reduction).  It
-// depends on one slot's work only, so a query's summation order -- and hence
-// its bits -- do not depend on how many other queries share the launch.
+// coarser (to amortize a block's set-up and its reduction).  It depends on
+// one slot's work only, so a query's summation order -- and hence its bits --
+// do not depend on how many other queries share the launch.
 int64_t group_entries_for(int64_t level_entries) {
-    return std::min<int64_t>(8192, std::max<int64_t>(1024, level_entries / 2048));
+    return std::min<int64_t>(JT_GROUP_MAX, std::max<int64_t>(JT_GROUP_MIN, level_entries / JT_GROUP_DIV));
 }
 
-// Blocks over the items [i0, i1) of one launch: each block takes `gpb`
-// consecutive groups of one item, about kTargetBlocks blocks per launch.
+// Blocks over the items [i0, i1) of one launch: each block takes
+// consecutive groups of one item, one after the other, so that every block
+// streams about the same number of entries and the launch has about
+// kTargetBlocks blocks (one round of resident blocks: each block's set-up
+// latency is paid once per launch, not once per small group).  Groups per
+// block change no summation order.
 void emit_tasks(Plan &P, int32_t i0, int32_t i1) {
-    int64_t groups = 0;
-    for (int32_t i = i0; i < i1; ++i) groups += P.items[i].n_groups;
-    groups *= P.n_slots;
-    const int64_t per = (groups + kTargetBlocks - 1) / kTargetBlocks;
-    const int32_t gpb = (int32_t)std::max<int64_t>(
-        JT_WAVES_PER_BLOCK, (per + JT_WAVES_PER_BLOCK - 1) / JT_WAVES_PER_BLOCK * JT_WAVES_PER_BLOCK);
-    for (int32_t i = i0; i < i1; ++i)
+    int64_t entries = 0;
+    for (int32_t i = i0; i < i1; ++i) entries += (int64_t)P.items[i].T * P.items[i].n_tiles;
+    entries *= P.n_slots;
+    const int64_t target = std::max<int64_t>(JT_GROUP_MIN, entries / kTargetBlocks);
+    for (int32_t i = i0; i < i1; ++i) {
+        const int64_t ge = (int64_t)P.items[i].tpg * P.items[i].T;   // entries of a full group
+        const int32_t gpb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(P.items[i].n_groups, target / ge));
         for (int32_t g0 = 0; g0 < P.items[i].n_groups; g0 += gpb) {
             P.items[i].n_tasks++;
             JtTask t;
@@ -211,6 +231,7 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1) {
             t.pad = 0;
             P.tasks.push_back(t);
         }
+    }
 }
 
 int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t dst_kind,
@@ -271,15 +292,25 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         // split partials (nsplit x |phi_S| floats) stay below 1/32 of the
         // table, or one separator table when that is larger
         const int64_t cap = std::max<int64_t>(V.ssize, std::min<int64_t>(kPartialMax, C.size / 32));
+        if (V.n_rout <= JT_WAVE_GROUP_TILES && V.n_kout > 1) {
+            // short groups: one per kept-outer configuration, a wave each,
+            // streamed back to back (one partial row, nsplit = 1)
+            it.wave_groups = 1;
+            it.tpg = V.n_rout;
+            it.nsplit = 1;
+            it.n_groups = V.n_kout;
+        }
         int64_t tpg = std::min<int64_t>(V.n_rout, tiles_per_group);
         int64_t nsplit = (V.n_rout + tpg - 1) / tpg;
         while (nsplit * V.ssize > cap && tpg < V.n_rout) {
             tpg *= 2;
             nsplit = (V.n_rout + tpg - 1) / tpg;
         }
-        it.tpg = (int32_t)tpg;
-        it.nsplit = (int32_t)nsplit;
-        it.n_groups = (int32_t)(V.n_kout * nsplit);
+        if (!it.wave_groups) {
+            it.tpg = (int32_t)tpg;
+            it.nsplit = (int32_t)nsplit;
+            it.n_groups = (int32_t)(V.n_kout * nsplit);
+        }
     } else {
         const int64_t tpg = std::min<int64_t>(C.n_tiles, tiles_per_group);
         it.tpg = (int32_t)tpg;
@@ -297,33 +328,6 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
 
 int32_t item_nsplit(const Plan &P, int32_t item) { return P.items[item].nsplit; }
 
-
-// Cut the finalize of message `mi` into blocks: jc separator entries per
-// block (a power of two), JT_BLOCK / jc split rows, at most ~8 rows per thread.
-void add_ftasks(Plan &P, int32_t mi, int64_t &fsig_count) {
-    JtMsg &m = P.msgs[mi];
-    int32_t rows = 1;
-    while (rows < JT_BLOCK && (int64_t)rows * 8 < m.nsplit) rows <<= 1;
-    int32_t jc = JT_BLOCK / rows;
-    int32_t sp2 = 1;
-    while (sp2 < m.ssize && sp2 < JT_BLOCK) sp2 <<= 1;
-    if (sp2 < jc) jc = sp2;
-    const int32_t nb = (m.ssize + jc - 1) / jc;
-    m.fbase = (int32_t)fsig_count;
-    m.nfb = nb;
-    fsig_count += nb;
-    for (int32_t b = 0; b < nb; ++b) {
-        JtFTask f;
-        std::memset(&f, 0, sizeof(f));
-        f.msg = mi;
-        f.j0 = b * jc;
-        f.j1 = std::min<int32_t>(m.ssize, (b + 1) * jc);
-        f.jc = jc;
-        f.b = b;
-        f.nb = nb;
-        P.ftasks.push_back(f);
-    }
-}
 
 // Check, on the host, that every index the kernels derive from the plan
 // stays inside its buffer.  Run once per compiled tree; a failure here is a
@@ -391,6 +395,8 @@ bool verify_plan(const Plan &P, std::string &why) {
         }
         if (it.scale_clique >= P.n_cliques) return bad("scale clique");
         if (it.tpg < 1 || it.nsplit < 1 || it.n_groups < 1) return bad("grouping");
+        if (it.wave_groups && (it.out_view < 0 || it.nsplit != 1 || it.tpg != it.o_n_rout || it.tpg > JT_WAVE_GROUP_TILES))
+            return bad("wave groups");
         if (it.out_view >= 0) {
             if (it.out_view >= (int32_t)P.views.size()) return bad("output view");
             const JtView &V = P.views[it.out_view];
@@ -438,49 +444,14 @@ bool verify_plan(const Plan &P, std::string &why) {
         }
         if (m.child_base < 0 || m.child_base + m.n_children > (int32_t)P.child_edges.size()) return bad("children range");
     }
-    for (const JtFTask &f : P.ftasks) {
-        if (f.msg < 0 || f.msg >= (int32_t)P.msgs.size()) return bad("finalize message");
-        const JtMsg &m = P.msgs[f.msg];
-        if (f.jc < 1 || f.jc > JT_BLOCK || (f.jc & (f.jc - 1))) return bad("finalize columns");
-        if (f.j0 < 0 || f.j0 >= f.j1 || f.j1 > m.ssize || f.j1 - f.j0 > f.jc) return bad("finalize range");
-        if (f.nb != m.nfb || f.b < 0 || f.b >= f.nb) return bad("finalize block");
-        if (m.fbase < 0 || m.fbase + m.nfb > P.fsig_stride) return bad("finalize scratch");
-    }
-    if ((int64_t)P.msgs.size() > P.fcnt_stride) return bad("finalize counters");
-    for (const JtUnit &u : P.units) {
-        if (u.kind == 0 && (u.index < 0 || u.index >= (int32_t)P.tasks.size() || P.tasks[u.index].item >= P.n_fused_items))
-            return bad("unit task");
-        if (u.kind == 1 && (u.index < 0 || u.index >= (int32_t)P.ftasks.size())) return bad("unit ftask");
-    }
-    // every dependency points to a message finalized by an earlier unit
-    {
-        std::vector<int32_t> done_at(P.msgs.size(), -1);
-        for (size_t k = 0; k < P.units.size(); ++k)
-            if (P.units[k].kind == 1) done_at[P.ftasks[P.units[k].index].msg] = (int32_t)k;
-        for (size_t k = 0; k < P.units.size(); ++k) {
-            if (P.units[k].kind != 0) continue;
-            const JtItem &it = P.items[P.tasks[P.units[k].index].item];
-            if (it.dep_base < 0 || it.dep_base + it.n_dep > (int32_t)P.deps.size()) return bad("dependency range");
-            for (int32_t a = 0; a < it.n_dep; ++a) {
-                const int32_t mi = P.deps[it.dep_base + a];
-                if (mi < 0 || mi >= (int32_t)P.msgs.size() || done_at[mi] < 0 || done_at[mi] >= (int32_t)k)
-                    return bad("dependency order");
-            }
-        }
-        for (size_t k = 0; k < P.units.size(); ++k) {
-            if (P.units[k].kind != 1) continue;
-            const JtMsg &m = P.msgs[P.ftasks[P.units[k].index].msg];
-            if (m.item < 0 || m.item >= P.n_fused_items) return bad("message item");
-            int32_t seen = 0;
-            for (size_t q = 0; q < k; ++q)
-                if (P.units[q].kind == 0 && P.tasks[P.units[q].index].item == m.item) ++seen;
-            if (seen != P.items[m.item].n_tasks) return bad("message item tasks");
-        }
-    }
-    for (const std::vector<Launch> *L : {&P.fused, &P.fused_split, &P.plain})
+    for (const std::vector<Launch> *L : {&P.fused, &P.plain})
         for (const Launch &l : *L) {
             if (l.is_pass == 1 && (l.begin < 0 || l.begin + l.count > (int32_t)P.tasks.size())) return bad("launch tasks");
-            if (l.is_pass == 0 && (l.begin < 0 || l.begin + l.count > (int32_t)P.ftasks.size())) return bad("launch ftasks");
+            if (l.is_pass == 1) {
+                if (l.lds_floats < JT_FIN_LDS_FLOATS || l.lds_floats > JT_LDS_RATIO_FLOATS) return bad("launch LDS");
+                for (int32_t t = l.begin; t < l.begin + l.count; ++t)
+                    if (P.items[P.tasks[t].item].lds_floats > l.lds_floats) return bad("launch LDS of an item");
+            }
         }
     for (int32_t c = 0; c < P.n_cliques; ++c)
         for (const VDigit &d : P.cl[c].digits)
@@ -649,8 +620,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         by_depth[P.cl[c].depth].push_back(c);
     }
     int64_t bytes = 0;
-    int64_t fsig_count = 0;
-    std::vector<int32_t> coll_msg(nc, -1), dist_msg(nc, -1);   // message into each clique's parent / from it
     for (int32_t h = 0; h <= P.height; ++h) {
         const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
         int64_t level_entries = 0;
@@ -667,10 +636,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             // item first with a placeholder, then patch its offset.
             const int32_t it = add_item(P, c, JT_SRC_INIT, C.init_off, C.children.empty() ? JT_DST_NONE : JT_DST_COLL,
                                         C.coll_off, gs, -1, view, 0, bytes, ge);
-            P.items[it].dep_base = (int32_t)P.deps.size();
-            for (int32_t ch : C.children) P.deps.push_back(coll_msg[ch]);
-            P.items[it].n_dep = (int32_t)C.children.size();
-            coll_msg[c] = m0 + (int32_t)level_msgs.size();
             const int64_t ss = P.views[view].ssize;
             const int64_t poff = add_partial(ss * item_nsplit(P, it));
             P.items[it].partial_off = poff;
@@ -694,10 +659,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         }
         emit_tasks(P, i0, (int32_t)P.items.size());
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
-        const int32_t f0 = (int32_t)P.ftasks.size();
-        for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
-        P.fused_split.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        P.fused_split.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
     }
     for (int32_t d = 0; d <= P.depth; ++d) {
@@ -714,16 +675,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             const bool leaf = C.children.empty();
             const int32_t src_kind = leaf ? JT_SRC_INIT : JT_SRC_COLL;
             const int64_t src_off = leaf ? C.init_off : C.coll_off;
-            // every distribute pass of c waits for the message that gives c
-            // its output scale: parent -> c, or the root's total
-            const int32_t dep = (c == P.root) ? coll_msg[c] : dist_msg[c];
-            auto set_dep = [&](int32_t item) {
-                P.items[item].dep_base = (int32_t)P.deps.size();
-                P.deps.push_back(dep);
-                P.items[item].n_dep = 1;
-            };
             if (leaf) {
-                set_dep(add_item(P, c, src_kind, src_off, JT_DST_OUT, C.out_off, gs, c, -1, 0, bytes, ge));
+                add_item(P, c, src_kind, src_off, JT_DST_OUT, C.out_off, gs, c, -1, 0, bytes, ge);
                 continue;
             }
             for (size_t k = 0; k < C.children.size(); ++k) {
@@ -731,8 +684,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                 const int32_t view = P.edge[ch].view_parent;
                 const int32_t it = add_item(P, c, src_kind, src_off, k == 0 ? JT_DST_OUT : JT_DST_NONE,
                                             C.out_off, gs, c, view, 0, bytes, ge);
-                set_dep(it);
-                dist_msg[ch] = m0 + (int32_t)level_msgs.size();
                 const int64_t ss = P.views[view].ssize;
                 const int64_t poff = add_partial(ss * item_nsplit(P, it));
                 P.items[it].partial_off = poff;
@@ -754,20 +705,10 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         }
         emit_tasks(P, i0, (int32_t)P.items.size());
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
-        const int32_t f0 = (int32_t)P.ftasks.size();
-        for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
-        P.fused_split.push_back({1, t0, (int32_t)P.tasks.size() - t0});
-        if (!level_msgs.empty()) P.fused_split.push_back({0, f0, (int32_t)P.ftasks.size() - f0});
         P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
     }
     P.bytes_fused = bytes;
 
-    // dataflow order: the fused launches' tasks and finalize tasks, in order
-    for (const Launch &l : P.fused_split)
-        for (int32_t x = l.begin; x < l.begin + l.count; ++x) P.units.push_back({l.is_pass ? 0 : 1, x});
-    P.n_fused_items = (int32_t)P.items.size();
-
-    // ---------------- one-message-at-a-time schedule ----------------
     // Tables live in the output region and are updated in place.
     bytes = 0;
     {
@@ -806,7 +747,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         m.sepd_off = P.edge[e].sepd_off;
         P.msgs.push_back(m);
         P.items[it].msg = (int32_t)P.msgs.size() - 1;
-        add_ftasks(P, (int32_t)P.msgs.size() - 1, fsig_count);
         const int32_t t1 = (int32_t)P.tasks.size();
         const int32_t it2 = add_item(P, to, JT_SRC_OUT, P.cl[to].out_off, JT_DST_OUT, P.cl[to].out_off, {{e, true}},
                                      -1, -1, 0, bytes, group_entries_for(P.cl[to].size));
@@ -844,7 +784,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     {
         // read-out: totals of every calibrated table, then normalize in place
         const int32_t t0 = (int32_t)P.tasks.size();
-        const int32_t m0 = (int32_t)P.msgs.size();
         const int32_t i0 = (int32_t)P.items.size();
         const int64_t ge = group_entries_for(P.total_entries);
         for (int32_t c = 0; c < nc; ++c) {
@@ -865,7 +804,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             P.msgs.push_back(m);
             P.items[it].msg = (int32_t)P.msgs.size() - 1;
         }
-        for (int32_t mi = m0; mi < (int32_t)P.msgs.size(); ++mi) add_ftasks(P, mi, fsig_count);
         emit_tasks(P, i0, (int32_t)P.items.size());
         P.plain.push_back({1, t0, (int32_t)P.tasks.size() - t0});
         const int32_t t1 = (int32_t)P.tasks.size();
@@ -876,6 +814,14 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
     }
     P.bytes_plain = bytes;
+    for (std::vector<Launch> *L : {&P.fused, &P.plain})
+        for (Launch &l : *L) {
+            if (l.is_pass != 1) continue;
+            l.lds_floats = JT_FIN_LDS_FLOATS;
+            for (int32_t t = l.begin; t < l.begin + l.count; ++t)
+                l.lds_floats = std::max<int32_t>(l.lds_floats, P.items[P.tasks[t].item].lds_floats);
+            l.lds_floats = (int32_t)align_up(l.lds_floats, 64);
+        }
     for (std::vector<Launch> *L : {&P.fused, &P.plain})
         for (Launch &l : *L) {
             if (l.is_pass != 1 || l.count == 0) continue;
@@ -894,8 +840,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         return fail(err, JT_E_TOO_LARGE, "partial region too large");
 
     // ---------------- workspace layout ----------------
-    P.fsig_stride = align_up(std::max<int64_t>(1, fsig_count), 32);
-    P.fcnt_stride = align_up(std::max<int64_t>(1, (int64_t)P.msgs.size()), kAlignFloats);
     P.lam_stride = align_up(3 * (int64_t)nc + 1, 32);
     P.scale_stride = align_up(nc, kAlignFloats);
     P.ev_idx_stride = align_up((int64_t)nc + 1, kAlignFloats);
@@ -914,7 +858,6 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_tasks = region(P.tasks.size() * sizeof(JtTask));
     P.off_msgs = region(P.msgs.size() * sizeof(JtMsg));
     P.off_child = region(std::max<size_t>(1, P.child_edges.size()) * sizeof(int32_t));
-    P.off_ftasks = region(std::max<size_t>(1, P.ftasks.size()) * sizeof(JtFTask));
     P.off_init = region((size_t)P.init_floats * sizeof(float));
     P.off_coll = region(S * (size_t)P.coll_stride * sizeof(float));
     P.off_out = region(S * (size_t)P.out_stride * sizeof(float));
@@ -925,21 +868,14 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_flag = region(S * sizeof(int32_t));
     P.off_ev_idx = region(S * (size_t)P.ev_idx_stride * sizeof(int32_t));
     P.off_ev_ent = region(S * (size_t)P.ev_ent_stride * sizeof(JtEv));
-    P.off_units = region(std::max<size_t>(1, P.units.size()) * sizeof(JtUnit));
-    P.off_deps = region(std::max<size_t>(1, P.deps.size()) * sizeof(int32_t));
-    P.df_stride = align_up((int64_t)P.n_fused_items + (int64_t)P.msgs.size(), kAlignFloats);
-    P.off_df = region((size_t)(kAlignFloats + S * P.df_stride) * sizeof(int32_t));
     P.icnt_stride = align_up(std::max<int64_t>(1, (int64_t)P.items.size()), kAlignFloats);
     P.off_icnt = region(S * (size_t)P.icnt_stride * sizeof(int32_t));
-    P.off_fsig = region(S * (size_t)P.fsig_stride * sizeof(double));
-    P.off_fcnt = region(S * (size_t)P.fcnt_stride * sizeof(int32_t));
     P.total_bytes = off;
     P.slot_bytes = (size_t)P.coll_stride * sizeof(float) + (size_t)P.out_stride * sizeof(float) +
                    (size_t)P.sep_stride * sizeof(float) + (size_t)P.partial_stride * sizeof(float) +
                    (size_t)P.lam_stride * sizeof(double) + (size_t)P.scale_stride * sizeof(float) + sizeof(int32_t) +
                    (size_t)P.ev_idx_stride * sizeof(int32_t) + (size_t)P.ev_ent_stride * sizeof(JtEv) +
-                   (size_t)P.fsig_stride * sizeof(double) + (size_t)P.fcnt_stride * sizeof(int32_t) +
-                   (size_t)P.df_stride * sizeof(int32_t) + (size_t)P.icnt_stride * sizeof(int32_t);
+                   (size_t)P.icnt_stride * sizeof(int32_t);
     std::string why;
     if (!verify_plan(P, why)) return fail(err, JT_E_ARG, why);
     return JT_OK;

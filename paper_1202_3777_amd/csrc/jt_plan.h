@@ -44,9 +44,10 @@ struct EdgeInfo {                    // edge (c, parent[c]); id = c
 };
 
 struct Launch {
-    int32_t is_pass;        // 1 = pass kernel over tasks, 0 = finalize over ftasks, 2 = one-at-a-time set-up
-    int32_t begin, count;   // tasks or ftasks (per slot)
+    int32_t is_pass;        // 1 = pass kernel over tasks, 2 = one-at-a-time set-up
+    int32_t begin, count;   // tasks (per slot)
     int64_t bytes = 0;      // FP32 table bytes a pass launch reads and writes (all slots)
+    int32_t lds_floats = 0; // dynamic LDS of a pass launch (staged ratio tables, finalize scratch)
 };
 
 struct Plan {
@@ -65,26 +66,20 @@ struct Plan {
     std::vector<JtItem> items;
     std::vector<JtTask> tasks;
     std::vector<JtMsg> msgs;
-    std::vector<JtFTask> ftasks;
-    std::vector<JtUnit> units;       // dataflow order of the fused schedule
-    std::vector<int32_t> deps;
     std::vector<int32_t> child_edges;
     std::vector<Launch> fused;       // launch list of one fused propagation (finalize inside the passes)
-    std::vector<Launch> fused_split; // the same with separate finalize launches (dataflow units follow it)
     std::vector<Launch> plain;       // launch list of one one-at-a-time propagation
     int32_t plain_reset_task_begin = 0, plain_reset_task_count = 0;
-    int32_t n_fused_items = 0;       // items [0, n_fused_items) belong to the fused schedule
 
     // per-slot region sizes (elements)
     int64_t init_floats = 0, coll_stride = 0, out_stride = 0, sep_stride = 0,
             partial_stride = 0, lam_stride = 0, scale_stride = 0, ev_idx_stride = 0,
-            ev_ent_stride = 0, fsig_stride = 0, fcnt_stride = 0, df_stride = 0, icnt_stride = 0;
+            ev_ent_stride = 0, icnt_stride = 0;
     // byte offsets of every region inside the workspace
     size_t off_meta = 0, off_views = 0, off_gathers = 0, off_items = 0, off_tasks = 0,
            off_msgs = 0, off_child = 0, off_init = 0, off_coll = 0, off_out = 0, off_sep = 0,
            off_partial = 0, off_lam = 0, off_scale = 0, off_flag = 0, off_ev_idx = 0,
-           off_ev_ent = 0, off_ftasks = 0, off_fsig = 0, off_fcnt = 0, off_units = 0, off_deps = 0,
-           off_df = 0, off_icnt = 0, total_bytes = 0;
+           off_ev_ent = 0, off_icnt = 0, total_bytes = 0;
     size_t slot_bytes = 0;           // workspace bytes that scale with the slot count (per slot)
 
     // statistics
