@@ -182,7 +182,10 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *   JT_Q_FUSED_LAUNCH_BYTES (arg = launch index: FP32 table bytes of that
  *     pass launch),
  *   JT_Q_SLOT_BYTES (workspace bytes each slot adds),
- *   JT_Q_SHARED_BYTES (workspace bytes independent of the slot count).
+ *   JT_Q_SHARED_BYTES (workspace bytes independent of the slot count),
+ *   JT_Q_ROOT (the clique the schedules collect to and distribute from: a
+ *     center of the tree, i.e. the middle of a longest path, so the sweeps
+ *     have the fewest levels; the caller's root only orients the edges).
  * Errors: JT_E_ARG. */
 #define JT_Q_N_SLOTS 0
 #define JT_Q_TOTAL_ENTRIES 1
@@ -199,6 +202,7 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_FUSED_LAUNCH_BYTES 12
 #define JT_Q_SLOT_BYTES 13
 #define JT_Q_SHARED_BYTES 14
+#define JT_Q_ROOT 15
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and

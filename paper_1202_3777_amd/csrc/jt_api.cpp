@@ -416,6 +416,7 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
         case JT_Q_DEPTH: *out = P.depth + 1; break;
         case JT_Q_SLOT_BYTES: *out = (int64_t)P.slot_bytes; break;
         case JT_Q_SHARED_BYTES: *out = (int64_t)P.total_bytes - (int64_t)P.slot_bytes * P.n_slots; break;
+        case JT_Q_ROOT: *out = P.root; break;
         case JT_Q_FUSED_LAUNCH_KIND:
         case JT_Q_FUSED_LAUNCH_BYTES: {
             std::vector<const jt::Launch *> live;

@@ -27,7 +27,7 @@
 #define JT_FIN_BATCH 16           /* partial loads a finalize thread issues before using them */
 #endif
 #ifndef JT_UNROLL
-#define JT_UNROLL 4               /* tiles per batch; two batches in flight per wave */
+#define JT_UNROLL 3               /* tiles per batch; two batches in flight per wave */
 #endif
 #ifndef JT_WAVE_GROUP_TILES
 #define JT_WAVE_GROUP_TILES 16    /* output views with at most this many tiles per kept-outer configuration use wave groups */

@@ -19,13 +19,13 @@ namespace {
 constexpr int64_t kAlignFloats = 64;       // 256-byte alignment of every table
 // Tuning constants (overridable at build time for sweeps).
 #ifndef JT_TARGET_BLOCKS
-#define JT_TARGET_BLOCKS 1024
+#define JT_TARGET_BLOCKS 1280
 #endif
 #ifndef JT_PARTIAL_MAX
 #define JT_PARTIAL_MAX 16384
 #endif
 #ifndef JT_GROUP_MIN
-#define JT_GROUP_MIN 4096
+#define JT_GROUP_MIN 8192
 #endif
 #ifndef JT_GROUP_MAX
 #define JT_GROUP_MAX 32768
@@ -546,10 +546,70 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                             "running intersection violated for variable " + std::to_string(v));
         }
     }
+    // Re-root at a center of the tree (the middle of a longest path): the
+    // collect / distribute sweeps then have the fewest levels.  Any clique
+    // may serve as the root of Algorithms 2-4; the messages between two
+    // cliques, the posteriors and P(e) do not depend on the choice.
+    {
+        std::vector<std::vector<int32_t>> adj(nc);
+        for (int32_t c = 0; c < nc; ++c)
+            if (P.parent[c] >= 0) {
+                adj[c].push_back(P.parent[c]);
+                adj[P.parent[c]].push_back(c);
+            }
+        for (auto &a : adj) std::sort(a.begin(), a.end());
+        std::vector<int32_t> dist(nc), from(nc);
+        auto farthest = [&](int32_t s0) {
+            std::fill(dist.begin(), dist.end(), -1);
+            std::vector<int32_t> q{s0};
+            dist[s0] = 0;
+            from[s0] = -1;
+            int32_t best = s0;
+            for (size_t h = 0; h < q.size(); ++h) {
+                const int32_t x = q[h];
+                if (dist[x] > dist[best]) best = x;
+                for (int32_t y : adj[x])
+                    if (dist[y] < 0) {
+                        dist[y] = dist[x] + 1;
+                        from[y] = x;
+                        q.push_back(y);
+                    }
+            }
+            return best;
+        };
+        const int32_t a = farthest(P.root);
+        const int32_t b = farthest(a);
+        int32_t center = b;
+        for (int32_t k = 0; k < dist[b] / 2; ++k) center = from[center];
+        P.user_root = P.root;
+        P.root = center;
+        P.iparent.assign(nc, -1);
+        P.iedge.assign(nc, -1);
+        for (int32_t c = 0; c < nc; ++c) {
+            P.cl[c].children.clear();
+            P.cl[c].depth = 0;
+            P.cl[c].height = 0;
+        }
+        bfs.assign(1, P.root);
+        std::vector<char> seen(nc, 0);
+        seen[P.root] = 1;
+        for (size_t h = 0; h < bfs.size(); ++h) {
+            const int32_t x = bfs[h];
+            for (int32_t y : adj[x]) {
+                if (seen[y]) continue;
+                seen[y] = 1;
+                P.iparent[y] = x;
+                P.iedge[y] = (P.parent[y] == x) ? y : x;   // the caller's child end of the edge
+                P.cl[x].children.push_back(y);
+                P.cl[y].depth = P.cl[x].depth + 1;
+                bfs.push_back(y);
+            }
+        }
+    }
     for (size_t h = bfs.size(); h-- > 0;) {
         const int32_t c = bfs[h];
-        if (P.parent[c] >= 0)
-            P.cl[P.parent[c]].height = std::max(P.cl[P.parent[c]].height, P.cl[c].height + 1);
+        const int32_t p = P.iparent[c];
+        if (p >= 0) P.cl[p].height = std::max(P.cl[p].height, P.cl[c].height + 1);
     }
     P.height = P.cl[P.root].height;
     for (int32_t c = 0; c < nc; ++c) P.depth = std::max(P.depth, P.cl[c].depth);
@@ -603,11 +663,14 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         if (P.parent[c] >= 0) {
             P.edge[c].view_child = build_view(P, c, c);
             P.edge[c].view_parent = build_view(P, P.parent[c], c);
-            P.cl[c].parent_view = P.edge[c].view_child;
         }
         P.cl[c].total_view = build_view(P, c, -1);
         if ((int64_t)P.meta.size() > kMaxMeta) return fail(err, JT_E_TOO_LARGE, "index metadata too large");
     }
+    // clique c seen through edge e (c is one of its two ends)
+    auto view_of = [&](int32_t c, int32_t e) { return c == e ? P.edge[e].view_child : P.edge[e].view_parent; };
+    for (int32_t c = 0; c < nc; ++c)
+        if (P.iparent[c] >= 0) P.cl[c].parent_view = view_of(c, P.iedge[c]);
     // ---------------- fused level schedule ----------------
     auto add_partial = [&](int64_t floats) {
         const int64_t off = P.partial_stride;
@@ -629,7 +692,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         for (int32_t c : by_height[h]) {
             const CliqueInfo &C = P.cl[c];
             std::vector<GatherSpec> gs;
-            for (int32_t ch : C.children) gs.push_back({ch, false});
+            for (int32_t ch : C.children) gs.push_back({P.iedge[ch], false});
             const bool is_root = (c == P.root);
             const int32_t view = is_root ? C.total_view : C.parent_view;
             // partial size is known once the item's split is chosen: add the
@@ -644,17 +707,17 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             m.item = it;
             P.items[it].msg = m0 + (int32_t)level_msgs.size();
             m.kind = is_root ? JT_MSG_TOTAL : JT_MSG_COLLECT;
-            m.edge = is_root ? -1 : c;
+            m.edge = is_root ? -1 : P.iedge[c];
             m.from = c;
-            m.to = is_root ? -1 : P.parent[c];
+            m.to = is_root ? -1 : P.iparent[c];
             m.ssize = (int32_t)ss;
             m.nsplit = P.items[it].nsplit;
             m.partial_off = poff;
             m.child_base = (int32_t)P.child_edges.size();
             m.n_children = (int32_t)C.children.size();
-            for (int32_t ch : C.children) P.child_edges.push_back(ch);
-            m.sepc_off = is_root ? 0 : P.edge[c].sepc_off;
-            m.sepd_off = is_root ? 0 : P.edge[c].sepd_off;
+            for (int32_t ch : C.children) P.child_edges.push_back(P.iedge[ch]);
+            m.sepc_off = is_root ? 0 : P.edge[P.iedge[c]].sepc_off;
+            m.sepd_off = is_root ? 0 : P.edge[P.iedge[c]].sepd_off;
             level_msgs.push_back(m);
         }
         emit_tasks(P, i0, (int32_t)P.items.size());
@@ -671,7 +734,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         for (int32_t c : by_depth[d]) {
             const CliqueInfo &C = P.cl[c];
             std::vector<GatherSpec> gs;
-            if (c != P.root) gs.push_back({c, true});
+            if (c != P.root) gs.push_back({P.iedge[c], true});
             const bool leaf = C.children.empty();
             const int32_t src_kind = leaf ? JT_SRC_INIT : JT_SRC_COLL;
             const int64_t src_off = leaf ? C.init_off : C.coll_off;
@@ -681,7 +744,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             }
             for (size_t k = 0; k < C.children.size(); ++k) {
                 const int32_t ch = C.children[k];
-                const int32_t view = P.edge[ch].view_parent;
+                const int32_t e = P.iedge[ch];
+                const int32_t view = view_of(c, e);
                 const int32_t it = add_item(P, c, src_kind, src_off, k == 0 ? JT_DST_OUT : JT_DST_NONE,
                                             C.out_off, gs, c, view, 0, bytes, ge);
                 const int64_t ss = P.views[view].ssize;
@@ -692,14 +756,14 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                 m.item = it;
                 P.items[it].msg = m0 + (int32_t)level_msgs.size();
                 m.kind = JT_MSG_DIST;
-                m.edge = ch;
+                m.edge = e;
                 m.from = c;
                 m.to = ch;
                 m.ssize = (int32_t)ss;
                 m.nsplit = P.items[it].nsplit;
                 m.partial_off = poff;
-                m.sepc_off = P.edge[ch].sepc_off;
-                m.sepd_off = P.edge[ch].sepd_off;
+                m.sepc_off = P.edge[e].sepc_off;
+                m.sepd_off = P.edge[e].sepd_off;
                 level_msgs.push_back(m);
             }
         }
@@ -765,7 +829,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             } else {
                 const int32_t c = top.first;
                 stack.pop_back();
-                if (P.parent[c] >= 0) plain_message(c, c, P.parent[c]);
+                if (P.iparent[c] >= 0) plain_message(P.iedge[c], c, P.iparent[c]);
             }
         }
         std::vector<std::pair<int32_t, size_t>> st2{{P.root, 0}};
@@ -774,7 +838,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             const CliqueInfo &C = P.cl[top.first];
             if (top.second < C.children.size()) {
                 const int32_t ch = C.children[top.second++];
-                plain_message(ch, top.first, ch);
+                plain_message(P.iedge[ch], top.first, ch);
                 st2.push_back({ch, 0});
             } else {
                 st2.pop_back();

@@ -30,9 +30,9 @@ struct CliqueInfo {
     int64_t n_tiles = 1;
     int64_t init_off = 0, coll_off = -1, out_off = 0;
     int32_t height = 0, depth = 0;
-    std::vector<int32_t> children;   // ascending id
+    std::vector<int32_t> children;   // ascending id, schedule orientation
     int32_t total_view = -1;
-    int32_t parent_view = -1;        // this clique through its parent separator
+    int32_t parent_view = -1;        // this clique through the separator to its schedule parent
 };
 
 struct EdgeInfo {                    // edge (c, parent[c]); id = c
@@ -57,6 +57,12 @@ struct Plan {
     std::vector<CliqueInfo> cl;
     std::vector<EdgeInfo> edge;
     std::vector<int32_t> home;       // lowest clique id holding each variable
+    // The schedules run on the tree re-rooted at a center clique (fewest
+    // levels); edges keep the caller's ids (the child clique of the caller's
+    // orientation).  iparent / iedge: parent in the schedule's orientation and
+    // the id of the edge to it; user_root: the caller's root.
+    std::vector<int32_t> iparent, iedge;
+    int32_t user_root = -1;
     int32_t height = 0, depth = 0;
 
     // device metadata (host copies)

@@ -46,6 +46,7 @@ JT_Q_FUSED_LAUNCH_KIND = 11
 JT_Q_FUSED_LAUNCH_BYTES = 12
 JT_Q_SLOT_BYTES = 13
 JT_Q_SHARED_BYTES = 14
+JT_Q_ROOT = 15
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",

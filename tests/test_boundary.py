@@ -134,7 +134,31 @@ def test_call_order_and_argument_errors():
         jt.jt_query(h, 99)
 
 
-@pytest.mark.parametrize("name,kw", [("c1", {}), ("c4", dict(n_slots=1)), ("c2", dict(n_cliques=9))])
+def _orient(parent, root):
+    """Parents of the same tree hung from `root`, and each clique's eccentricity."""
+    n = len(parent)
+    adj = [[] for _ in range(n)]
+    for c in range(n):
+        if parent[c] >= 0:
+            adj[c].append(int(parent[c]))
+            adj[int(parent[c])].append(c)
+
+    def bfs(s):
+        d, par, q = [-1] * n, [-1] * n, [s]
+        d[s] = 0
+        for x in q:
+            for y in adj[x]:
+                if d[y] < 0:
+                    d[y], par[y] = d[x] + 1, x
+                    q.append(y)
+        return d, par
+
+    ecc = [max(bfs(s)[0]) for s in range(n)]
+    return np.array(bfs(root)[1]), ecc
+
+
+@pytest.mark.parametrize("name,kw", [("c1", {}), ("c4", dict(n_slots=1)), ("c2", dict(n_cliques=9)), ("c2", {}),
+                                     ("c3", {})])
 def test_schedule_facts(name, kw):
     inst = make_instance(name, 1, **kw)
     plan = jt.JunctionTreePlan.from_instance(inst)
@@ -142,11 +166,18 @@ def test_schedule_facts(name, kw):
     eps = sum(int(sizes[c] + sizes[inst.parent[c]]) for c in range(inst.n_cliques) if inst.parent[c] >= 0)
     assert plan.query(jt.JT_Q_ENTRIES_PER_SWEEP) == eps
     assert plan.query(jt.JT_Q_TOTAL_ENTRIES) == int(sizes.sum())
+    # the schedules collect to a center of the tree: its eccentricity is the
+    # radius, and the sweeps have radius + 1 levels each
+    root = plan.query(jt.JT_Q_ROOT)
+    sparent, ecc = _orient(inst.parent, root)
+    assert ecc[root] == min(ecc)
+    assert plan.query(jt.JT_Q_HEIGHT) == ecc[root] + 1 == plan.query(jt.JT_Q_DEPTH)
     # fused schedule bytes: every clique read once in collect (plus a write of
     # the absorbed table when it has children); in distribute a leaf reads its
     # initial table and writes its posterior, a clique with k children reads
-    # its absorbed table k times and writes its posterior once
-    kids = [np.count_nonzero(inst.parent == c) for c in range(inst.n_cliques)]
+    # its absorbed table k times and writes its posterior once (children in
+    # the schedule's orientation)
+    kids = [np.count_nonzero(sparent == c) for c in range(inst.n_cliques)]
     exp = 0
     for c in range(inst.n_cliques):
         b = 4 * int(sizes[c])
