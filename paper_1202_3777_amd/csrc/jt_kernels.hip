@@ -438,19 +438,66 @@ struct FinPtrs {
     int32_t n_cliques;
 };
 
+// Keep the loads above this point from being moved below it (and the uses
+// below from being moved above): the batch's loads are all in flight before
+// the first one is waited for.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
+// Column sums of the partial rows for columns j = jj + CT*(c0 + c), c < CB,
+// rows s = r + R*i: four accumulators per column (i mod 4) combined as
+// (a0 + a1) + (a2 + a3); RB rows per batch, so each batch issues CB*RB loads
+// before any is used.  Writes the sums to raw and returns their FP64 total.
+template <int CB, int RB>
+__device__ __forceinline__ double column_sums(const float *P, float *raw, int ssize, int CT, int R, int jj, int r,
+                                              int c0, int ncol, int nrow, float *first) {
+    float a[CB][4];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[c][q] = 0.f;
+    for (int i0 = 0; i0 < nrow; i0 += RB) {
+        float x[CB][RB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                x[c][q] = 0.f;
+                if (c0 + c < ncol && i0 + q < nrow) x[c][q] = ldp(P + (int64_t)(r + R * (i0 + q)) * ssize + jj + CT * (c0 + c));
+            }
+        issue_fence();
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int q = 0; q < RB; ++q) a[c][q] += x[c][q];   // row i0 + q, i0 a multiple of 4 or 0
+    }
+    double local = 0.0;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        const float v = (a[c][0] + a[c][1]) + (a[c][2] + a[c][3]);
+        if (c0 + c < ncol) {
+            if (R == 1) {
+                if (raw) raw[jj + CT * (c0 + c)] = v;
+                local += (double)v;
+            } else {
+                *first = v;   // one column per thread when R > 1
+            }
+        }
+    }
+    return local;
+}
+
 // The finalize of one message, in the block of its pass that arrived last.
 //  1. raw[j] = sum over the partial rows s of P[s][j], in a fixed order:
-//     thread (jj, r) owns columns j = jj + CT*c and rows s = r + R*i, keeps
-//     four accumulators (i mod 4) and issues up to 32 loads before using
-//     any; with R > 1 row groups the columns are combined in a fixed LDS tree;
+//     thread (jj, r) owns columns j = jj + CT*c and rows s = r + R*i (see
+//     column_sums); with R > 1 row groups the columns are combined in a fixed
+//     LDS tree;
 //  2. sigma = sum_j raw[j] in FP64 (fixed wave trees, waves in order);
-//  3. log-scales from sigma, then the separator table is written as the
+//  3. log-scales from sigma, then the separator table is rewritten as the
 //     collect table (rescaled to mean one) or the distribute ratio new/old
 //     with 0/0 := 0.
-// Columns c < 4 of each thread stay in registers between 1 and 3.  Every
-// load that does not depend on the partials (old separator entries, the
-// log-scales the update reads) is issued before the partials are used, so
-// the finalize costs about one memory round trip plus its stores.
+// The loads that do not depend on the partials (the log-scales the update
+// reads) are issued first; steps 1 and 3 each issue their loads in batches
+// before using them, so the finalize costs a few memory round trips.
 __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &m, int slot, PassLds &L) {
     const int tid = threadIdx.x;
     const int lane = tid & (JT_WAVE - 1), wave = tid / JT_WAVE;
@@ -474,18 +521,9 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
     const int jj = tid & (CT - 1), r = tid / CT;
     const int ncol = jj < ssize ? (ssize - jj + CT - 1) / CT : 0;
     const int nrow = r < nsplit ? (nsplit - r + R - 1) / R : 0;
-    const int total = ncol * nrow;
 
-    // independent loads first: old separator entries of the thread's kept
-    // columns, the children's collect log-scales (wave 0, one per lane), the
-    // log-scales tid 0 combines
-    const int nkeep = R == 1 ? min(ncol, 4) : (r == 0 && jj < ssize ? 1 : 0);
-    float od[4] = {0.f, 0.f, 0.f, 0.f};
-    if (oldc) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q < nkeep) od[q] = oldc[jj + CT * q];
-    }
+    // log-scales the update reads: the children's collect scales (wave 0,
+    // one per lane) and the ones tid 0 combines
     double lcv = 0.0;
     if (wave == 0 && (m.kind == JT_MSG_COLLECT || m.kind == JT_MSG_TOTAL))
         for (int a = lane; a < m.n_children; a += JT_WAVE) lcv += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
@@ -503,65 +541,36 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
         }
     }
 
-    float keepv[4] = {0.f, 0.f, 0.f, 0.f};
+    // 1. column sums; batch shape by the rows per thread (the shape depends
+    //    on the message only, so the order is fixed)
     double local = 0.0;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    int c = 0, i = 0;   // column and row of the next element, in order
-    for (int e0 = 0; e0 < total; e0 += JT_FIN_BATCH) {
-        float x[JT_FIN_BATCH];
-        {
-            int cc = c, ii = i;
-#pragma unroll
-            for (int u = 0; u < JT_FIN_BATCH; ++u) {
-                x[u] = 0.f;
-                if (e0 + u < total) {
-                    x[u] = ldp(P + (int64_t)(r + R * ii) * ssize + jj + CT * cc);
-                    if (++ii == nrow) {
-                        ii = 0;
-                        ++cc;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < JT_FIN_BATCH; ++u) {
-            if (e0 + u < total) {
-                switch (i & 3) {
-                    case 0: a0 += x[u]; break;
-                    case 1: a1 += x[u]; break;
-                    case 2: a2 += x[u]; break;
-                    default: a3 += x[u]; break;
-                }
-                if (++i == nrow) {
-                    const float v = (a0 + a1) + (a2 + a3);
-                    a0 = a1 = a2 = a3 = 0.f;
-                    i = 0;
-                    if (R == 1) {
-                        local += (double)v;
-                        if (c < 4) keepv[c & 3] = v;
-                        else if (raw) raw[jj + CT * c] = v;
-                    } else {
-                        keepv[0] = v;   // one column per thread
-                    }
-                    ++c;
-                }
-            }
+    float first = 0.f;
+    for (int c0 = 0; c0 < ncol;) {
+        if (nrow <= 1) {
+            local += column_sums<16, 1>(P, raw, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
+            c0 += 16;
+        } else if (nrow <= 2) {
+            local += column_sums<8, 2>(P, raw, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
+            c0 += 8;
+        } else {
+            local += column_sums<4, 4>(P, raw, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
+            c0 += 4;
         }
     }
     if (R > 1) {
         // combine the R row groups of each column (fixed tree)
         float *red = &L.red[0][0];
-        red[tid] = keepv[0];
+        red[tid] = first;
         __syncthreads();
         for (int h = R >> 1; h > 0; h >>= 1) {
             if (r < h) red[tid] += red[tid + h * CT];
             __syncthreads();
         }
-        keepv[0] = red[jj];
-        local = (r == 0 && jj < ssize) ? (double)keepv[0] : 0.0;
+        first = red[jj];
+        local = (r == 0 && jj < ssize) ? (double)first : 0.0;
     }
-    // sigma: wave trees, then the waves in order; the children's log-scales
-    // in a fixed tree too
+    // 2. sigma: wave trees, then the waves in order; the children's
+    //    log-scales in a fixed tree too
     local = wave_sum_lane0(local);
     if (lane == 0) L.wsum[wave] = local;
     const double lc = wave == 0 ? wave_sum_lane0(lcv) : 0.0;
@@ -631,8 +640,7 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
     __syncthreads();
     if (!raw) return;
     const float f = L.f;
-    // the thread's columns: c < nkeep from registers, the rest re-read
-    // (eight at a time, loads before stores)
+    // 3. rewrite the thread's columns, sixteen at a time (loads before stores)
     auto put = [&](int j, float v, float o) {
         const float nw = v * f;
         if (m.kind == JT_MSG_COLLECT) {
@@ -642,24 +650,25 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
             if (m.kind == JT_MSG_PLAIN) oldc[j] = nw;
         }
     };
+    if (R > 1) {
+        if (r == 0 && jj < ssize) put(jj, first, oldc ? oldc[jj] : 0.f);
+        return;
+    }
+    for (int q0 = 0; q0 < ncol; q0 += 16) {
+        float v16[16], o16[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (q < nkeep) put(jj + CT * q, keepv[q], od[q]);
-    const int ncol_w = R == 1 ? ncol : nkeep;
-    for (int q0 = 4; q0 < ncol_w; q0 += 8) {
-        float v8[8], o8[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            v8[u] = 0.f;
-            o8[u] = 0.f;
-            if (q0 + u < ncol_w) {
-                v8[u] = raw[jj + CT * (q0 + u)];
-                if (oldc) o8[u] = oldc[jj + CT * (q0 + u)];
+        for (int u = 0; u < 16; ++u) {
+            v16[u] = 0.f;
+            o16[u] = 0.f;
+            if (q0 + u < ncol) {
+                v16[u] = raw[jj + CT * (q0 + u)];
+                if (oldc) o16[u] = oldc[jj + CT * (q0 + u)];
             }
         }
+        issue_fence();
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (q0 + u < ncol_w) put(jj + CT * (q0 + u), v8[u], o8[u]);
+        for (int u = 0; u < 16; ++u)
+            if (q0 + u < ncol) put(jj + CT * (q0 + u), v16[u], o16[u]);
     }
 }
 

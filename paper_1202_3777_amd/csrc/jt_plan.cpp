@@ -218,10 +218,18 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1) {
     int64_t entries = 0;
     for (int32_t i = i0; i < i1; ++i) entries += (int64_t)P.items[i].T * P.items[i].n_tiles;
     entries *= P.n_slots;
-    const int64_t target = std::max<int64_t>(JT_GROUP_MIN, entries / kTargetBlocks);
+    // Entries per block, rounded up per item: each item adds at most one
+    // partly filled block per slot, which the budget leaves room for.  With
+    // many (item, slot) pairs every pair is a block anyway; then blocks are
+    // rounded down instead.
+    const int64_t extra = (int64_t)(i1 - i0) * P.n_slots;
+    const bool few = extra < kTargetBlocks / 2;
+    const int64_t budget = few ? kTargetBlocks - extra : kTargetBlocks;
+    const int64_t target = std::max<int64_t>(JT_GROUP_MIN, few ? (entries + budget - 1) / budget : entries / budget);
     for (int32_t i = i0; i < i1; ++i) {
         const int64_t ge = (int64_t)P.items[i].tpg * P.items[i].T;   // entries of a full group
-        const int32_t gpb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(P.items[i].n_groups, target / ge));
+        const int64_t want = few ? (target + ge - 1) / ge : target / ge;
+        const int32_t gpb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(P.items[i].n_groups, want));
         for (int32_t g0 = 0; g0 < P.items[i].n_groups; g0 += gpb) {
             P.items[i].n_tasks++;
             JtTask t;
