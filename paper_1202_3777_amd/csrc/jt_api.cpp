@@ -216,6 +216,7 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     if (e == hipSuccess) e = up(P.off_gathers, P.gathers.data(), P.gathers.size() * sizeof(JtGather));
     if (e == hipSuccess) e = up(P.off_items, P.items.data(), P.items.size() * sizeof(JtItem));
     if (e == hipSuccess) e = up(P.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(JtTask));
+    if (e == hipSuccess) e = up(P.off_blocks, P.blocks.data(), P.blocks.size() * sizeof(JtBlock));
     if (e == hipSuccess) e = up(P.off_msgs, P.msgs.data(), P.msgs.size() * sizeof(JtMsg));
     if (e == hipSuccess) e = up(P.off_child, P.child_edges.data(), P.child_edges.size() * sizeof(int32_t));
     // pass arrival counters start at zero; the block that finalizes a message
@@ -238,6 +239,7 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     d.gathers = region<JtGather>(t, P.off_gathers);
     d.items = region<JtItem>(t, P.off_items);
     d.tasks = region<JtTask>(t, P.off_tasks);
+    d.blocks = region<JtBlock>(t, P.off_blocks);
     d.msgs = region<JtMsg>(t, P.off_msgs);
     d.child_edges = region<int32_t>(t, P.off_child);
     d.icnt = reinterpret_cast<int32_t *>(t->ws + P.off_icnt);

@@ -92,6 +92,15 @@ typedef struct {
     int32_t item, g0, g1, pad;
 } JtTask;
 
+// What one block of a pass launch reads first, in one record: its task, a
+// copy of the item and of the item's first gathers (one dependent load
+// instead of three).
+typedef struct {
+    JtItem it;
+    JtGather g[JT_NG_REG];
+    int32_t item, g0, g1, pad;
+} JtBlock;
+
 enum {
     JT_MSG_COLLECT = 0,   // child -> parent, collect sweep
     JT_MSG_TOTAL = 1,     // root table total: log Z and the root's output scale
@@ -134,6 +143,7 @@ typedef struct {
     const JtGather *gathers;
     const JtItem *items;
     const JtTask *tasks;
+    const JtBlock *blocks;
     const JtMsg *msgs;
     const int32_t *child_edges;
     const float *init;

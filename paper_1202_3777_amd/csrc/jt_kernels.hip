@@ -114,6 +114,7 @@ __device__ __forceinline__ void fold_store(const float *row, const PassLds &L, i
 // One block's share of a pass: groups [task.g0, task.g1) of item `it`.
 template <int VEC>
 __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task, int slot,
+                                           const JtGather *__restrict__ gfirst,
                                            const JtGather *__restrict__ gathers, const int32_t *__restrict__ meta,
                                            const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
                                            const float *__restrict__ init, float *__restrict__ coll,
@@ -148,7 +149,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
 #pragma unroll
         for (int q = 0; q < 4; ++q) jin[g][q] = 0;
         if (g < ngr) {
-            const JtGather G = gathers[it.gather_base + g];
+            const JtGather G = gfirst[g];
             gr[g].jout_off = G.jout_off;
             gr[g].in_lds = G.lds_off >= 0;
             gr[g].off = G.lds_off >= 0 ? G.lds_off : G.sep_off;
@@ -191,7 +192,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     float *part = partial + (int64_t)slot * st.partial + it.partial_off;
 
     // issue the loads of chunk tiles [u0, min(u0 + U, nt))
-    auto issue = [&](TileBatch &B, int u0, int nt, int my_o, uint64_t zmask) {
+    auto issue = [&](TileBatch &B, int u0, int nt, int my_o) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
             const int uu = u0 + u;
@@ -199,31 +200,33 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
 #pragma unroll
             for (int q = 0; q < 4; ++q) B.x[u][q] = 0.f;
             if (uu < nt) {
+                // loaded even when evidence zeroes the tile (masked in
+                // consume), so the load does not wait for the evidence test
                 const int o = __builtin_amdgcn_readlane(my_o, uu);
                 B.o[u] = o;
-                if (!((zmask >> uu) & 1ull)) {
-                    const float *base = src + (int64_t)o * T;
-                    if (VEC == 4) {
-                        if (valid[0]) {
-                            const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
-                            B.x[u][0] = v4.x;
-                            B.x[u][1] = v4.y;
-                            B.x[u][2] = v4.z;
-                            B.x[u][3] = v4.w;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if (valid[q]) B.x[u][q] = base[pos[q]];
+                const float *base = src + (int64_t)o * T;
+                if (VEC == 4) {
+                    if (valid[0]) {
+                        const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
+                        B.x[u][0] = v4.x;
+                        B.x[u][1] = v4.y;
+                        B.x[u][2] = v4.z;
+                        B.x[u][3] = v4.w;
                     }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (valid[q]) B.x[u][q] = base[pos[q]];
                 }
             }
         }
     };
     // tile u of batch B (chunk tile uu): multiply in the gathers, mask,
     // scale, store, accumulate
-    auto consume_one = [&](const TileBatch &B, int u, int uu, const int (&my_jo)[JT_NG_REG], float (&acc)[4]) {
+    auto consume_one = [&](const TileBatch &B, int u, int uu, uint64_t zmask, const int (&my_jo)[JT_NG_REG],
+                           float (&acc)[4]) {
         {
+            const bool zt = (zmask >> uu) & 1ull;   // outer evidence zeroes the whole tile
             const int o = B.o[u];
             float v[4];
 #pragma unroll
@@ -251,7 +254,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = keep[q] ? v[q] * scale : 0.f;
+            for (int q = 0; q < 4; ++q) v[q] = (keep[q] && !zt) ? v[q] * scale : 0.f;
             if (dst) {
                 float *b = dst + (int64_t)o * T;
                 if (VEC == 4) {
@@ -266,11 +269,12 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             for (int q = 0; q < 4; ++q) acc[q] += v[q];
         }
     };
-    auto consume = [&](const TileBatch &B, int u0, int nt, const int (&my_jo)[JT_NG_REG], float (&acc)[4]) {
+    auto consume = [&](const TileBatch &B, int u0, int nt, uint64_t zmask, const int (&my_jo)[JT_NG_REG],
+                       float (&acc)[4]) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
             if (u0 + u >= nt) break;
-            consume_one(B, u, u0 + u, my_jo, acc);
+            consume_one(B, u, u0 + u, zmask, my_jo, acc);
         }
     };
 
@@ -278,7 +282,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     // calls it once, after its first chunk's tile loads are in flight
     auto stage = [&]() {
         for (int gg = 0; gg < it.n_gather_lds; ++gg) {
-            const JtGather G = gathers[it.gather_base + gg];
+            const JtGather G = gg < JT_NG_REG ? gfirst[gg] : gathers[it.gather_base + gg];
             for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = sep_slot[G.sep_off + j];
         }
         if (has_out) {
@@ -313,7 +317,8 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = 0.f;
         };
-        auto consume_w = [&](const TileBatch &Bt, int u0, int nt, int my_g, int my_jk, const int (&my_jo)[JT_NG_REG]) {
+        auto consume_w = [&](const TileBatch &Bt, int u0, int nt, int my_g, int my_jk, uint64_t zmask,
+                             const int (&my_jo)[JT_NG_REG]) {
 #pragma unroll
             for (int u = 0; u < JT_UNROLL; ++u) {
                 const int uu = u0 + u;
@@ -324,7 +329,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                     cur_g = gt;
                     cur_jk = __builtin_amdgcn_readlane(my_jk, uu);
                 }
-                consume_one(Bt, u, uu, my_jo, acc);
+                consume_one(Bt, u, uu, zmask, my_jo, acc);
             }
         };
         bool staged = false;
@@ -349,16 +354,16 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             int my_jo[JT_NG_REG];
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) my_jo[gg] = (gg < ngr && live) ? meta[gr[gg].jout_off + my_o] : 0;
-            issue(A, 0, nt, my_o, zmask);
+            issue(A, 0, nt, my_o);
             if (!staged) {
                 stage();
                 staged = true;
             }
             for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
-                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o, zmask);
-                consume_w(A, uq, nt, my_g, my_jk, my_jo);
-                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o, zmask);
-                if (uq + JT_UNROLL < nt) consume_w(B, uq + JT_UNROLL, nt, my_g, my_jk, my_jo);
+                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
+                consume_w(A, uq, nt, my_g, my_jk, zmask, my_jo);
+                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
+                if (uq + JT_UNROLL < nt) consume_w(B, uq + JT_UNROLL, nt, my_g, my_jk, zmask, my_jo);
             }
             cb += JT_WAVE;
         } while (cb < n_my);
@@ -398,17 +403,17 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             int my_jo[JT_NG_REG];
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) my_jo[gg] = (gg < ngr && live) ? meta[gr[gg].jout_off + my_o] : 0;
-            issue(A, 0, nt, my_o, zmask);
+            issue(A, 0, nt, my_o);
             if (!staged) {
                 stage();
                 staged = true;
             }
             // two batches of tiles in flight: load one while the other is consumed
             for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
-                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o, zmask);
-                consume(A, uq, nt, my_jo, acc);
-                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o, zmask);
-                if (uq + JT_UNROLL < nt) consume(B, uq + JT_UNROLL, nt, my_jo, acc);
+                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
+                consume(A, uq, nt, zmask, my_jo, acc);
+                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
+                if (uq + JT_UNROLL < nt) consume(B, uq + JT_UNROLL, nt, zmask, my_jo, acc);
             }
             cb += JT_WAVE;
         } while (cb < b);
@@ -685,7 +690,7 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
 // the log-scales and the new table or ratio.  No block ever waits for
 // another, and the next level's launch sees finished messages.
 extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
-    const JtTask *__restrict__ tasks, const JtItem *__restrict__ items, const JtGather *__restrict__ gathers,
+    const JtBlock *__restrict__ blocks, const JtGather *__restrict__ gathers,
     const int32_t *__restrict__ meta, const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
     const float *__restrict__ init, float *__restrict__ coll, float *__restrict__ out, float *__restrict__ sep,
     float *__restrict__ scale, float *__restrict__ partial, const JtMsg *__restrict__ msgs,
@@ -696,13 +701,18 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
     extern __shared__ __align__(16) float lds_ratio[];
     __shared__ PassLds L;
     const int slot = blockIdx.x / n_tasks;
-    const JtTask task = tasks[task_begin + (blockIdx.x - slot * n_tasks)];
-    const JtItem it = items[task.item];
+    const JtBlock *__restrict__ rec = blocks + task_begin + (blockIdx.x - slot * n_tasks);
+    const JtItem it = rec->it;
+    JtTask task;
+    task.item = rec->item;
+    task.g0 = rec->g0;
+    task.g1 = rec->g1;
+    task.pad = 0;
     if (it.vec == 4)
-        pass_block<4>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
+        pass_block<4>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
                       lds_ratio, L);
     else
-        pass_block<1>(it, task, slot, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
+        pass_block<1>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
                       lds_ratio, L);
     if (it.msg < 0) return;
     const JtMsg m = msgs[it.msg];   // in flight while the stores drain
@@ -752,7 +762,7 @@ hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slo
     st.ev_idx = d.ev_idx_stride;
     st.ev_ent = d.ev_ent_stride;
     hipLaunchKernelGGL(jt_pass_kernel, dim3((unsigned)n_tasks * (unsigned)n_slots), dim3(JT_BLOCK),
-                       (size_t)lds_floats * sizeof(float), s, d.tasks, d.items, d.gathers, d.meta, d.ev_idx,
+                       (size_t)lds_floats * sizeof(float), s, d.blocks, d.gathers, d.meta, d.ev_idx,
                        d.ev_ent, d.init, d.coll, d.out, d.sep, d.scale, d.partial, d.msgs, d.child_edges, d.lam,
                        d.flag, d.icnt, st, d.lam_stride, d.icnt_stride, d.n_cliques, task_begin, n_tasks);
     return hipGetLastError();

@@ -439,6 +439,17 @@ bool verify_plan(const Plan &P, std::string &why) {
         if (t.item < 0 || t.item >= (int32_t)P.items.size()) return bad("task item");
         if (t.g0 < 0 || t.g1 > P.items[t.item].n_groups || t.g0 >= t.g1) return bad("task groups");
     }
+    if (P.blocks.size() != P.tasks.size()) return bad("block records");
+    for (size_t k = 0; k < P.tasks.size(); ++k) {
+        const JtTask &t = P.tasks[k];
+        const JtBlock &b = P.blocks[k];
+        if (b.item != t.item || b.g0 != t.g0 || b.g1 != t.g1 ||
+            std::memcmp(&b.it, &P.items[t.item], sizeof(JtItem)) != 0)
+            return bad("block record copy");
+        for (int g = 0; g < JT_NG_REG && g < b.it.n_gather; ++g)
+            if (std::memcmp(&b.g[g], &P.gathers[b.it.gather_base + g], sizeof(JtGather)) != 0)
+                return bad("block gather copy");
+    }
     for (const JtMsg &m : P.msgs) {
         if (m.ssize < 1 || m.nsplit < 1) return bad("message shape");
         if (m.partial_off < 0 || m.partial_off + (int64_t)m.nsplit * m.ssize > P.partial_stride) return bad("message partial");
@@ -911,6 +922,19 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     if (P.partial_stride > std::numeric_limits<int32_t>::max() * int64_t(4))
         return fail(err, JT_E_TOO_LARGE, "partial region too large");
 
+    // per-block records: the task, its item and the item's first gathers
+    P.blocks.resize(P.tasks.size());
+    for (size_t k = 0; k < P.tasks.size(); ++k) {
+        JtBlock &b = P.blocks[k];
+        std::memset(&b, 0, sizeof(b));
+        const JtTask &t = P.tasks[k];
+        b.it = P.items[t.item];
+        for (int g = 0; g < JT_NG_REG && g < b.it.n_gather; ++g) b.g[g] = P.gathers[b.it.gather_base + g];
+        b.item = t.item;
+        b.g0 = t.g0;
+        b.g1 = t.g1;
+    }
+
     // ---------------- workspace layout ----------------
     P.lam_stride = align_up(3 * (int64_t)nc + 1, 32);
     P.scale_stride = align_up(nc, kAlignFloats);
@@ -928,6 +952,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_gathers = region(std::max<size_t>(1, P.gathers.size()) * sizeof(JtGather));
     P.off_items = region(P.items.size() * sizeof(JtItem));
     P.off_tasks = region(P.tasks.size() * sizeof(JtTask));
+    P.off_blocks = region(std::max<size_t>(1, P.blocks.size()) * sizeof(JtBlock));
     P.off_msgs = region(P.msgs.size() * sizeof(JtMsg));
     P.off_child = region(std::max<size_t>(1, P.child_edges.size()) * sizeof(int32_t));
     P.off_init = region((size_t)P.init_floats * sizeof(float));

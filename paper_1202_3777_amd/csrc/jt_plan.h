@@ -71,6 +71,7 @@ struct Plan {
     std::vector<JtGather> gathers;
     std::vector<JtItem> items;
     std::vector<JtTask> tasks;
+    std::vector<JtBlock> blocks;     // device records of the tasks (same order)
     std::vector<JtMsg> msgs;
     std::vector<int32_t> child_edges;
     std::vector<Launch> fused;       // launch list of one fused propagation (finalize inside the passes)
@@ -82,7 +83,7 @@ struct Plan {
             partial_stride = 0, lam_stride = 0, scale_stride = 0, ev_idx_stride = 0,
             ev_ent_stride = 0, icnt_stride = 0;
     // byte offsets of every region inside the workspace
-    size_t off_meta = 0, off_views = 0, off_gathers = 0, off_items = 0, off_tasks = 0,
+    size_t off_meta = 0, off_views = 0, off_gathers = 0, off_items = 0, off_tasks = 0, off_blocks = 0,
            off_msgs = 0, off_child = 0, off_init = 0, off_coll = 0, off_out = 0, off_sep = 0,
            off_partial = 0, off_lam = 0, off_scale = 0, off_flag = 0, off_ev_idx = 0,
            off_ev_ent = 0, off_icnt = 0, total_bytes = 0;
