@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--mode", default="graph", choices=["graph", "fused", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="pick the schedule's shape choices by measurement first (auto: batched c4 only)")
+    ap.add_argument("--tuning", default=None, help="JSON of jt_tuning fields, instead of autotuning")
     ap.add_argument("--queries", type=int, default=2000, help="c5: queries per arrival-rate run")
     ap.add_argument("--capacity", type=int, default=8, help="c5: evidence slots per resident tree")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="c5: HBM admission budget")
@@ -76,15 +79,18 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}))
 
 
-def measured_traffic(cfg, kernel):
+def measured_traffic(cfg, kernel, tuning=None):
     """HBM bytes per launch from the committed counter runs, or None when the
-    kernel source changed since they were taken."""
+    kernel source or the schedule's shape choices differ from those the
+    counters were taken with."""
     from paper_1202_3777_amd.rocprof_summary import kernel_source_hash
     f = TRAFFIC_FILE.format(cfg=cfg)
     if not os.path.exists(f):
         return None
     t = json.load(open(f))
     if t.get("source_sha256") != kernel_source_hash() or t.get("kernel") != kernel:
+        return None
+    if (tuning or {}) != t.get("tuning", {}):
         return None
     return t["traffic_bytes_per_launch"]
 
@@ -176,7 +182,17 @@ def main():
         return
     log(f"[bench] generating {args.config} seed {args.seed}")
     inst = make_instance(args.config, args.seed)
-    tree = jt.JunctionTree.from_instance(inst, device="cuda:0")
+    tuning, tune_table = {}, None
+    if args.tuning:
+        tuning = json.loads(args.tuning)
+    elif args.autotune == "on" or (args.autotune == "auto" and args.config == "c4"):
+        from paper_1202_3777_amd import tune
+        log("[bench] autotuning the schedule's shape choices (untimed)")
+        tuning, tune_table = tune.autotune(inst, mode=args.mode if args.mode != "plain" else "graph")
+        for cand, ms in tune_table:
+            log(f"[bench]   {json.dumps(cand):60s} {ms:.4f} ms")
+        log(f"[bench] chosen: {json.dumps(tuning)}")
+    tree = jt.JunctionTree.from_instance(inst, device="cuda:0", tuning=tuning)
     stream = tree.stream
     n_slots = tree.n_slots
     entries = 2 * tree.query(jt.JT_Q_ENTRIES_PER_SWEEP) * n_slots     # both sweeps, all slots
@@ -267,10 +283,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "seed": args.seed,
-                   "n_slots": n_slots, "schedule": args.mode, "parallelism": "single GPU"},
+                   "n_slots": n_slots, "schedule": args.mode, "parallelism": "single GPU",
+                   "tuning": tuning or "defaults", "lanes": tree.query(jt.JT_Q_N_LANES),
+                   "autotune_ms": None if tune_table is None else [[c, round(ms, 4)] for c, ms in tune_table]},
         "hbm_gbs_table_bytes": (bytes_fused if args.mode != "plain" else bytes_plain) / (ms * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config, kernel_name),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config, kernel_name, tuning),
                      "kernel": kernel_name, "launches_per_step": n_pass,
                      "avg_launch_us": avg_launch_ms * 1e3, "bytes_per_launch": bytes_per_launch},
         "plain_sweep": None if ms_plain is None else {

@@ -82,6 +82,23 @@ typedef int32_t jt_status;
 
 typedef struct jt_tree_s *jt_tree;
 
+/* Shape choices of the fused schedule (all in table entries or blocks; 0
+ * selects the built-in default).  They change how the work is cut, never
+ * what is computed; results stay within the stated tolerance for every
+ * choice and are bit-identical from run to run for a given choice.
+ *   group_min, group_max  bounds of a group (the entries one block reduces
+ *                         into one partial row), defaults 8192 and 32768;
+ *   group_div             a level's entries per slot / group_div is the
+ *                         group size before the bounds, default 1024;
+ *   target_blocks         blocks per launch aimed for, default 1280 (one
+ *                         round of resident blocks);
+ *   max_lanes             streams for the root's subtrees (1 = all levels
+ *                         on the bound stream); lanes are disabled in this
+ *                         version: values above 1 return JT_E_ARG. */
+typedef struct {
+    int32_t group_min, group_max, group_div, target_blocks, max_lanes;
+} jt_tuning;
+
 typedef struct {
     int32_t n_vars;
     const int32_t *card;        /* [n_vars], each >= 1 */
@@ -90,6 +107,7 @@ typedef struct {
     const int32_t *clique_vars; /* [clique_off[n_cliques]], no repeats within a clique */
     const int32_t *parent;      /* [n_cliques], exactly one -1 */
     int32_t n_slots;            /* evidence sets propagated together, >= 1 */
+    const jt_tuning *tuning;    /* NULL: defaults (copied at compile) */
 } jt_tree_desc;
 
 /* Validate the tree and precompute every cluster-separator index mapping
@@ -185,7 +203,12 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *   JT_Q_SHARED_BYTES (workspace bytes independent of the slot count),
  *   JT_Q_ROOT (the clique the schedules collect to and distribute from: a
  *     center of the tree, i.e. the middle of a longest path, so the sweeps
- *     have the fewest levels; the caller's root only orients the edges).
+ *     have the fewest levels; the caller's root only orients the edges),
+ *   JT_Q_N_LANES (streams the fused schedule spreads the root's subtrees
+ *     over, 0 when everything runs on the bound stream),
+ *   JT_Q_CLIQUE_LANE (arg = clique: its lane, -1 for the root or without lanes),
+ *   JT_Q_FUSED_LAUNCH_LANE (arg = launch index: the lane it runs on, -1 for
+ *     the bound stream).
  * Errors: JT_E_ARG. */
 #define JT_Q_N_SLOTS 0
 #define JT_Q_TOTAL_ENTRIES 1
@@ -203,6 +226,9 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_SLOT_BYTES 13
 #define JT_Q_SHARED_BYTES 14
 #define JT_Q_ROOT 15
+#define JT_Q_N_LANES 16
+#define JT_Q_CLIQUE_LANE 17
+#define JT_Q_FUSED_LAUNCH_LANE 18
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and

@@ -46,6 +46,10 @@ struct jt_tree_s {
     std::vector<JtEv> ev_ent_host;      // [n_slots][ev_ent_stride]
     // captured graphs of the level launches, keyed by the number of active slots
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // lane streams of the fused schedule (default priority, created at bind)
+    std::vector<hipStream_t> lane_stream;
+    std::vector<hipEvent_t> lane_done;
+    hipEvent_t fork_ev = nullptr;
     int last_mode = -1;
     int last_n_active = 0;
 };
@@ -90,18 +94,66 @@ jt_status upload_evidence(jt_tree t) {
     return JT_OK;
 }
 
+// Launch list L on the bound stream and, for launches of a lane, on that
+// lane's stream: the lanes first wait for the bound stream (fork), a launch
+// marked join_before first makes the bound stream wait for every lane, one
+// marked fork_after lets the lanes continue after it, and the bound stream
+// waits for every lane at the end.  Under stream capture this records a
+// graph whose lane branches run side by side.
 jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L, int S) {
-    for (const jt::Launch &l : L) {
+    bool lanes = false;
+    for (const jt::Launch &l : L) lanes = lanes || l.lane >= 0;
+    if (lanes && t->lane_stream.empty()) return set_err(JT_E_STATE, "lane streams missing");
+    auto fork = [&]() -> hipError_t {
+        hipError_t e = hipEventRecord(t->fork_ev, t->stream);
+        for (hipStream_t ls : t->lane_stream)
+            if (e == hipSuccess) e = hipStreamWaitEvent(ls, t->fork_ev, 0);
+        return e;
+    };
+    auto join = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
+        for (size_t k = 0; k < t->lane_stream.size() && e == hipSuccess; ++k) {
+            e = hipEventRecord(t->lane_done[k], t->lane_stream[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(t->stream, t->lane_done[k], 0);
+        }
+        return e;
+    };
+    hipError_t e = lanes ? fork() : hipSuccess;
+    if (e != hipSuccess) return hip_err(e, "lane fork");
+    for (const jt::Launch &l : L) {
+        if (l.join_before && lanes) {
+            e = join();
+            if (e != hipSuccess) return hip_err(e, "lane join");
+        }
+        hipStream_t s = l.lane >= 0 ? t->lane_stream[l.lane] : t->stream;
         if (l.is_pass == 2) {
-            e = jt_launch_plain_init(t->dev, S, t->stream);
+            e = jt_launch_plain_init(t->dev, S, s);
         } else if (l.count > 0) {
             if ((int64_t)l.count * S > 0x7fffffffLL) return set_err(JT_E_TOO_LARGE, "grid too large");
-            e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, t->stream);
+            e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, s);
         }
         if (e != hipSuccess) return hip_err(e, "kernel launch");
+        if (l.fork_after && lanes) {
+            e = fork();
+            if (e != hipSuccess) return hip_err(e, "lane fork");
+        }
+    }
+    if (lanes) {
+        e = join();
+        if (e != hipSuccess) return hip_err(e, "lane join");
     }
     return JT_OK;
+}
+
+void drop_lanes(jt_tree t) {
+    for (hipStream_t s : t->lane_stream)
+        if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : t->lane_done)
+        if (e) (void)hipEventDestroy(e);
+    if (t->fork_ev) (void)hipEventDestroy(t->fork_ev);
+    t->lane_stream.clear();
+    t->lane_done.clear();
+    t->fork_ev = nullptr;
 }
 
 void drop_graph(jt_tree t) {
@@ -203,6 +255,22 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     if (bytes < P.total_bytes)
         return set_err(JT_E_NO_MEM, "workspace of " + std::to_string(bytes) + " bytes, need " + std::to_string(P.total_bytes));
     drop_graph(t);
+    drop_lanes(t);
+    if (P.n_lanes > 0) {
+        hipError_t le = hipEventCreateWithFlags(&t->fork_ev, hipEventDisableTiming);
+        for (int32_t k = 0; k < P.n_lanes && le == hipSuccess; ++k) {
+            hipStream_t ls = nullptr;
+            hipEvent_t de = nullptr;
+            le = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking);
+            if (le == hipSuccess) t->lane_stream.push_back(ls);
+            if (le == hipSuccess) le = hipEventCreateWithFlags(&de, hipEventDisableTiming);
+            if (le == hipSuccess) t->lane_done.push_back(de);
+        }
+        if (le != hipSuccess) {
+            drop_lanes(t);
+            return hip_err(le, "lane streams");
+        }
+    }
     t->ws = static_cast<char *>(workspace);
     t->ws_bytes = bytes;
     t->stream = static_cast<hipStream_t>(hip_stream);
@@ -419,13 +487,21 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
         case JT_Q_SLOT_BYTES: *out = (int64_t)P.slot_bytes; break;
         case JT_Q_SHARED_BYTES: *out = (int64_t)P.total_bytes - (int64_t)P.slot_bytes * P.n_slots; break;
         case JT_Q_ROOT: *out = P.root; break;
+        case JT_Q_N_LANES: *out = P.n_lanes; break;
+        case JT_Q_CLIQUE_LANE:
+            if (arg < 0 || arg >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");
+            *out = P.lane[arg];
+            break;
         case JT_Q_FUSED_LAUNCH_KIND:
+        case JT_Q_FUSED_LAUNCH_LANE:
         case JT_Q_FUSED_LAUNCH_BYTES: {
             std::vector<const jt::Launch *> live;
             for (const jt::Launch &l : P.fused)
                 if (l.count > 0) live.push_back(&l);
             if (arg < 0 || arg >= (int64_t)live.size()) return set_err(JT_E_ARG, "launch index out of range");
-            *out = what == JT_Q_FUSED_LAUNCH_KIND ? live[arg]->is_pass : live[arg]->bytes;
+            *out = what == JT_Q_FUSED_LAUNCH_KIND   ? live[arg]->is_pass
+                   : what == JT_Q_FUSED_LAUNCH_LANE ? live[arg]->lane
+                                                    : live[arg]->bytes;
             break;
         }
         default: return set_err(JT_E_ARG, "unknown query");
@@ -509,6 +585,7 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
 void jt_free(jt_tree t) {
     if (!t) return;
     drop_graph(t);
+    drop_lanes(t);
     delete t;
 }
 

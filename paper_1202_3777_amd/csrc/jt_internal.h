@@ -29,6 +29,13 @@
 #ifndef JT_UNROLL
 #define JT_UNROLL 3               /* tiles per batch; two batches in flight per wave */
 #endif
+#ifndef JT_MAX_LANES
+#define JT_MAX_LANES 4            /* streams the fused schedule could spread the root's subtrees over */
+#endif
+/* Lanes are switched off: the first GPU run with them ended in a host-side
+ * segmentation fault inside a graph propagation (cause not found), so
+ * max_lanes must stay 1 and every level runs on the bound stream. */
+#define JT_LANES_ENABLED 0
 #ifndef JT_WAVE_GROUP_TILES
 #define JT_WAVE_GROUP_TILES 16    /* output views with at most this many tiles per kept-outer configuration use wave groups */
 #endif

@@ -33,7 +33,6 @@ constexpr int64_t kAlignFloats = 64;       // 256-byte alignment of every table
 #ifndef JT_GROUP_DIV
 #define JT_GROUP_DIV 1024
 #endif
-constexpr int64_t kTargetBlocks = JT_TARGET_BLOCKS;   // blocks per launch the grouping aims for
 constexpr int64_t kPartialMax = JT_PARTIAL_MAX;       // cap on split partial floats per message
 constexpr int64_t kMaxMeta = int64_t(1) << 30;
 
@@ -204,17 +203,18 @@ struct GatherSpec {
 // coarser (to amortize a block's set-up and its reduction).  It depends on
 // one slot's work only, so a query's summation order -- and hence its bits --
 // do not depend on how many other queries share the launch.
-int64_t group_entries_for(int64_t level_entries) {
-    return std::min<int64_t>(JT_GROUP_MAX, std::max<int64_t>(JT_GROUP_MIN, level_entries / JT_GROUP_DIV));
+int64_t group_entries_for(const Plan &P, int64_t level_entries) {
+    return std::min<int64_t>(P.tune.group_max, std::max<int64_t>(P.tune.group_min, level_entries / P.tune.group_div));
 }
 
 // Blocks over the items [i0, i1) of one launch: each block takes
 // consecutive groups of one item, one after the other, so that every block
 // streams about the same number of entries and the launch has about
-// kTargetBlocks blocks (one round of resident blocks: each block's set-up
+// `target_blocks` blocks (one round of resident blocks: each block's set-up
 // latency is paid once per launch, not once per small group).  Groups per
 // block change no summation order.
-void emit_tasks(Plan &P, int32_t i0, int32_t i1) {
+void emit_tasks(Plan &P, int32_t i0, int32_t i1, int64_t target_blocks) {
+    const int64_t tb = std::max<int64_t>(1, target_blocks);
     int64_t entries = 0;
     for (int32_t i = i0; i < i1; ++i) entries += (int64_t)P.items[i].T * P.items[i].n_tiles;
     entries *= P.n_slots;
@@ -223,9 +223,9 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1) {
     // many (item, slot) pairs every pair is a block anyway; then blocks are
     // rounded down instead.
     const int64_t extra = (int64_t)(i1 - i0) * P.n_slots;
-    const bool few = extra < kTargetBlocks / 2;
-    const int64_t budget = few ? kTargetBlocks - extra : kTargetBlocks;
-    const int64_t target = std::max<int64_t>(JT_GROUP_MIN, few ? (entries + budget - 1) / budget : entries / budget);
+    const bool few = extra < tb / 2;
+    const int64_t budget = few ? tb - extra : tb;
+    const int64_t target = std::max<int64_t>(P.tune.group_min, few ? (entries + budget - 1) / budget : entries / budget);
     for (int32_t i = i0; i < i1; ++i) {
         const int64_t ge = (int64_t)P.items[i].tpg * P.items[i].T;   // entries of a full group
         const int64_t want = few ? (target + ge - 1) / ge : target / ge;
@@ -475,6 +475,19 @@ bool verify_plan(const Plan &P, std::string &why) {
     for (int32_t c = 0; c < P.n_cliques; ++c)
         for (const VDigit &d : P.cl[c].digits)
             if (d.card < 1 || (d.outer ? d.ostride : d.stride) < 1) return bad("digit shape");
+    // lanes: every launch's items belong to the launch's lane; the root's
+    // launches are on the bound stream, the collect one joins, the distribute
+    // one forks
+    if (P.n_lanes < 0 || P.n_lanes > JT_MAX_LANES || (int32_t)P.lane.size() != P.n_cliques) return bad("lanes");
+    for (const Launch &l : P.fused) {
+        if (l.lane < -1 || l.lane >= std::max(1, P.n_lanes) || (P.n_lanes == 0 && l.lane != -1)) return bad("launch lane");
+        for (int32_t t = l.begin; t < l.begin + l.count; ++t)
+            if (P.lane[P.items[P.tasks[t].item].clique] != l.lane) return bad("item lane");
+        const bool root = l.count > 0 && P.items[P.tasks[l.begin].item].clique == P.root;
+        if (P.n_lanes > 0 && root != (l.join_before || l.fork_after)) return bad("lane sync");
+    }
+    for (const Launch &l : P.plain)
+        if (l.lane != -1 || l.join_before || l.fork_after) return bad("plain lanes");
     return true;
 }
 
@@ -489,6 +502,24 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     if ((nv > 0 && !desc->card) || !desc->clique_off || !desc->clique_vars || !desc->parent)
         return fail(err, JT_E_ARG, "NULL array in desc");
     P = Plan();
+    {
+        jt_tuning d{JT_GROUP_MIN, JT_GROUP_MAX, JT_GROUP_DIV, JT_TARGET_BLOCKS, JT_LANES_ENABLED ? JT_MAX_LANES : 1};
+        if (desc->tuning) {
+            const jt_tuning &u = *desc->tuning;
+            if (u.group_min < 0 || u.group_max < 0 || u.group_div < 0 || u.target_blocks < 0 || u.max_lanes < 0 ||
+                u.max_lanes > JT_MAX_LANES || u.group_div > (1 << 20) || u.target_blocks > (1 << 20))
+                return fail(err, JT_E_ARG, "tuning value out of range");
+            if (u.group_min) d.group_min = u.group_min;
+            if (u.group_max) d.group_max = u.group_max;
+            if (u.group_div) d.group_div = u.group_div;
+            if (u.target_blocks) d.target_blocks = u.target_blocks;
+            if (u.max_lanes) d.max_lanes = u.max_lanes;
+        }
+        if (d.group_min > d.group_max) return fail(err, JT_E_ARG, "tuning: group_min above group_max");
+        if (!JT_LANES_ENABLED && d.max_lanes > 1)
+            return fail(err, JT_E_ARG, "tuning: lanes are disabled (max_lanes must be 1)");
+        P.tune = d;
+    }
     P.n_vars = nv;
     P.n_cliques = nc;
     P.n_slots = desc->n_slots;
@@ -654,6 +685,33 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             P.coll_stride += align_up(C.size, kAlignFloats);
         }
     }
+    // lanes: the root's subtrees, largest first, each to the lane with the
+    // least work so far (ties to the lower lane)
+    {
+        P.lane.assign(nc, -1);
+        const std::vector<int32_t> &rk = P.cl[P.root].children;
+        std::vector<int64_t> sub(nc, 0);
+        for (size_t h = bfs.size(); h-- > 0;) {
+            const int32_t c = bfs[h];
+            sub[c] += P.cl[c].size;
+            if (P.iparent[c] >= 0) sub[P.iparent[c]] += sub[c];
+        }
+        P.n_lanes = (rk.size() >= 2 && P.tune.max_lanes >= 2)
+                        ? (int32_t)std::min<size_t>((size_t)P.tune.max_lanes, rk.size())
+                        : 0;
+        if (P.n_lanes > 0) {
+            std::vector<int32_t> order(rk.begin(), rk.end());
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return sub[a] > sub[b]; });
+            std::vector<int64_t> load(P.n_lanes, 0);
+            for (int32_t ch : order) {
+                const int32_t l = (int32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                load[l] += sub[ch];
+                P.lane[ch] = l;
+            }
+            for (int32_t c : bfs)
+                if (c != P.root && P.lane[c] < 0) P.lane[c] = P.lane[P.iparent[c]];
+        }
+    }
     // separators: ascending variable id, row-major, last fastest
     P.edge.resize(nc);
     for (int32_t c = 0; c < nc; ++c) {
@@ -702,13 +760,40 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         by_depth[P.cl[c].depth].push_back(c);
     }
     int64_t bytes = 0;
+    // cliques of one level, lane by lane (the root is alone on its level)
+    auto split_lanes = [&](const std::vector<int32_t> &level) {
+        std::vector<std::vector<int32_t>> out(std::max(1, P.n_lanes) + 1);
+        for (int32_t c : level) out[P.lane[c] + 1].push_back(c);
+        return out;   // [0]: the root; [l + 1]: lane l
+    };
+    // a launch of a lane gets its share of one round of resident blocks
+    auto lane_target = [&](int64_t part, int64_t level_total) {
+        const int64_t tb = P.tune.target_blocks;
+        if (P.n_lanes == 0 || level_total <= 0) return tb;
+        return std::max<int64_t>(tb / 8, tb * part / level_total);
+    };
+    auto push_launch = [&](int32_t t0, int32_t lane, int32_t join, int32_t fork) {
+        Launch l;
+        l.is_pass = 1;
+        l.begin = t0;
+        l.count = (int32_t)P.tasks.size() - t0;
+        l.lane = lane;
+        l.join_before = join;
+        l.fork_after = fork;
+        P.fused.push_back(l);
+    };
     for (int32_t h = 0; h <= P.height; ++h) {
-        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
         int64_t level_entries = 0;
         for (int32_t c : by_height[h]) level_entries += P.cl[c].size;
-        const int64_t ge = group_entries_for(level_entries);
+        const int64_t ge = group_entries_for(P, level_entries);
+        const auto parts = split_lanes(by_height[h]);
+        for (size_t li = 0; li < parts.size(); ++li) {
+        if (parts[li].empty()) continue;
+        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
+        int64_t part_entries = 0;
+        for (int32_t c : parts[li]) part_entries += P.cl[c].size;
         std::vector<JtMsg> level_msgs;
-        for (int32_t c : by_height[h]) {
+        for (int32_t c : parts[li]) {
             const CliqueInfo &C = P.cl[c];
             std::vector<GatherSpec> gs;
             for (int32_t ch : C.children) gs.push_back({P.iedge[ch], false});
@@ -739,18 +824,26 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             m.sepd_off = is_root ? 0 : P.edge[P.iedge[c]].sepd_off;
             level_msgs.push_back(m);
         }
-        emit_tasks(P, i0, (int32_t)P.items.size());
+        emit_tasks(P, i0, (int32_t)P.items.size(), lane_target(part_entries, level_entries));
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
-        P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        // the root's collect pass first joins every lane
+        push_launch(t0, (int32_t)li - 1, li == 0 && P.n_lanes > 0 ? 1 : 0, 0);
+        }
     }
     for (int32_t d = 0; d <= P.depth; ++d) {
-        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
         int64_t level_entries = 0;
         for (int32_t c : by_depth[d])
             level_entries += P.cl[c].size * std::max<int64_t>(1, (int64_t)P.cl[c].children.size());
-        const int64_t ge = group_entries_for(level_entries);
+        const int64_t ge = group_entries_for(P, level_entries);
+        const auto parts = split_lanes(by_depth[d]);
+        for (size_t li = 0; li < parts.size(); ++li) {
+        if (parts[li].empty()) continue;
+        const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
+        int64_t part_entries = 0;
+        for (int32_t c : parts[li])
+            part_entries += P.cl[c].size * std::max<int64_t>(1, (int64_t)P.cl[c].children.size());
         std::vector<JtMsg> level_msgs;
-        for (int32_t c : by_depth[d]) {
+        for (int32_t c : parts[li]) {
             const CliqueInfo &C = P.cl[c];
             std::vector<GatherSpec> gs;
             if (c != P.root) gs.push_back({P.iedge[c], true});
@@ -786,9 +879,11 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
                 level_msgs.push_back(m);
             }
         }
-        emit_tasks(P, i0, (int32_t)P.items.size());
+        emit_tasks(P, i0, (int32_t)P.items.size(), lane_target(part_entries, level_entries));
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
-        P.fused.push_back({1, t0, (int32_t)P.tasks.size() - t0});
+        // after the root's distribute pass every lane waits for it
+        push_launch(t0, (int32_t)li - 1, 0, li == 0 && P.n_lanes > 0 ? 1 : 0);
+        }
     }
     P.bytes_fused = bytes;
 
@@ -797,10 +892,10 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     {
         const int32_t t0 = (int32_t)P.tasks.size();
         const int32_t i0 = (int32_t)P.items.size();
-        const int64_t ge = group_entries_for(P.total_entries);
+        const int64_t ge = group_entries_for(P, P.total_entries);
         for (int32_t c = 0; c < nc; ++c)
             add_item(P, c, JT_SRC_INIT, P.cl[c].init_off, JT_DST_OUT, P.cl[c].out_off, {}, -1, -1, 0, bytes, ge);
-        emit_tasks(P, i0, (int32_t)P.items.size());
+        emit_tasks(P, i0, (int32_t)P.items.size(), P.tune.target_blocks);
         P.plain_reset_task_begin = t0;
         P.plain_reset_task_count = (int32_t)P.tasks.size() - t0;
         P.plain.push_back({2, 0, 0});   // separators := 1, log-scales := 0
@@ -810,8 +905,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         const int32_t view_from = (from == e) ? P.edge[e].view_child : P.edge[e].view_parent;
         const int32_t t0 = (int32_t)P.tasks.size();
         const int32_t it = add_item(P, from, JT_SRC_OUT, P.cl[from].out_off, JT_DST_NONE, 0, {}, -1,
-                                    view_from, 0, bytes, group_entries_for(P.cl[from].size));
-        emit_tasks(P, it, it + 1);
+                                    view_from, 0, bytes, group_entries_for(P, P.cl[from].size));
+        emit_tasks(P, it, it + 1, P.tune.target_blocks);
         const int64_t ss = P.edge[e].ssize;
         const int64_t poff = add_partial(ss * item_nsplit(P, it));
         P.items[it].partial_off = poff;
@@ -832,8 +927,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         P.items[it].msg = (int32_t)P.msgs.size() - 1;
         const int32_t t1 = (int32_t)P.tasks.size();
         const int32_t it2 = add_item(P, to, JT_SRC_OUT, P.cl[to].out_off, JT_DST_OUT, P.cl[to].out_off, {{e, true}},
-                                     -1, -1, 0, bytes, group_entries_for(P.cl[to].size));
-        emit_tasks(P, it2, it2 + 1);
+                                     -1, -1, 0, bytes, group_entries_for(P, P.cl[to].size));
+        emit_tasks(P, it2, it2 + 1, P.tune.target_blocks);
         P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
     };
     // Algorithm 2 (post-order) and Algorithm 3 (pre-order), children ascending
@@ -868,7 +963,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         // read-out: totals of every calibrated table, then normalize in place
         const int32_t t0 = (int32_t)P.tasks.size();
         const int32_t i0 = (int32_t)P.items.size();
-        const int64_t ge = group_entries_for(P.total_entries);
+        const int64_t ge = group_entries_for(P, P.total_entries);
         for (int32_t c = 0; c < nc; ++c) {
             const int32_t view = P.cl[c].total_view;
             const int32_t it = add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_NONE, 0, {}, -1, view, 0, bytes, ge);
@@ -887,13 +982,13 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             P.msgs.push_back(m);
             P.items[it].msg = (int32_t)P.msgs.size() - 1;
         }
-        emit_tasks(P, i0, (int32_t)P.items.size());
+        emit_tasks(P, i0, (int32_t)P.items.size(), P.tune.target_blocks);
         P.plain.push_back({1, t0, (int32_t)P.tasks.size() - t0});
         const int32_t t1 = (int32_t)P.tasks.size();
         const int32_t i1 = (int32_t)P.items.size();
         for (int32_t c = 0; c < nc; ++c)
             add_item(P, c, JT_SRC_OUT, P.cl[c].out_off, JT_DST_OUT, P.cl[c].out_off, {}, c, -1, 0, bytes, ge);
-        emit_tasks(P, i1, (int32_t)P.items.size());
+        emit_tasks(P, i1, (int32_t)P.items.size(), P.tune.target_blocks);
         P.plain.push_back({1, t1, (int32_t)P.tasks.size() - t1});
     }
     P.bytes_plain = bytes;

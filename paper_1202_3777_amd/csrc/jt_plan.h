@@ -48,9 +48,14 @@ struct Launch {
     int32_t begin, count;   // tasks (per slot)
     int64_t bytes = 0;      // FP32 table bytes a pass launch reads and writes (all slots)
     int32_t lds_floats = 0; // dynamic LDS of a pass launch (staged ratio tables, finalize scratch)
+    int32_t lane = -1;      // stream: -1 the bound stream, else the lane of a root subtree
+    int32_t join_before = 0;  // the bound stream first waits for every lane
+    int32_t fork_after = 0;   // every lane then waits for the bound stream
 };
 
 struct Plan {
+    // shape choices (defaults filled in)
+    jt_tuning tune{};
     // tree
     int32_t n_vars = 0, n_cliques = 0, n_slots = 1, root = -1;
     std::vector<int32_t> card, parent;
@@ -63,6 +68,11 @@ struct Plan {
     // the id of the edge to it; user_root: the caller's root.
     std::vector<int32_t> iparent, iedge;
     int32_t user_root = -1;
+    // Lanes: the root's subtrees, grouped into at most JT_MAX_LANES sets of
+    // about equal work; each lane's levels run on a stream of their own, so
+    // one subtree's launch tail overlaps another's streaming.
+    std::vector<int32_t> lane;       // per clique, -1 for the root
+    int32_t n_lanes = 0;
     int32_t height = 0, depth = 0;
 
     // device metadata (host copies)

@@ -47,6 +47,9 @@ JT_Q_FUSED_LAUNCH_BYTES = 12
 JT_Q_SLOT_BYTES = 13
 JT_Q_SHARED_BYTES = 14
 JT_Q_ROOT = 15
+JT_Q_N_LANES = 16
+JT_Q_CLIQUE_LANE = 17
+JT_Q_FUSED_LAUNCH_LANE = 18
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
@@ -59,11 +62,19 @@ class JTError(RuntimeError):
         self.code = code
 
 
+class jt_tuning(ctypes.Structure):
+    _fields_ = [("group_min", ctypes.c_int32), ("group_max", ctypes.c_int32), ("group_div", ctypes.c_int32),
+                ("target_blocks", ctypes.c_int32), ("max_lanes", ctypes.c_int32)]
+
+
+TUNING_FIELDS = [f for f, _ in jt_tuning._fields_]
+
+
 class jt_tree_desc(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("card", ctypes.POINTER(ctypes.c_int32)),
                 ("n_cliques", ctypes.c_int32), ("clique_off", ctypes.POINTER(ctypes.c_int64)),
                 ("clique_vars", ctypes.POINTER(ctypes.c_int32)), ("parent", ctypes.POINTER(ctypes.c_int32)),
-                ("n_slots", ctypes.c_int32)]
+                ("n_slots", ctypes.c_int32), ("tuning", ctypes.POINTER(jt_tuning))]
 
 
 _lib = None
@@ -115,15 +126,21 @@ def _p(a: np.ndarray, ct):
 # --------------------------------------------------------------------------
 # one-to-one wrappers of the C ABI
 
-def jt_compile_index_maps(card, clique_off, clique_vars, parent, n_slots: int = 1):
-    """Returns (handle, device_bytes, keepalive)."""
+def jt_compile_index_maps(card, clique_off, clique_vars, parent, n_slots: int = 1, tuning: Optional[dict] = None):
+    """Returns (handle, device_bytes).  `tuning`: jt_tuning fields by name (missing or 0 = default)."""
     lib = load()
     card = np.ascontiguousarray(card, dtype=np.int32)
     off = np.ascontiguousarray(clique_off, dtype=np.int64)
     cv = np.ascontiguousarray(clique_vars, dtype=np.int32)
     par = np.ascontiguousarray(parent, dtype=np.int32)
+    tptr = None
+    if tuning:
+        unknown = set(tuning) - set(TUNING_FIELDS)
+        if unknown:
+            raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+        tptr = ctypes.pointer(jt_tuning(*[int(tuning.get(f, 0)) for f in TUNING_FIELDS]))
     d = jt_tree_desc(int(card.shape[0]), _p(card, ctypes.c_int32), int(par.shape[0]), _p(off, ctypes.c_int64),
-                     _p(cv, ctypes.c_int32), _p(par, ctypes.c_int32), int(n_slots))
+                     _p(cv, ctypes.c_int32), _p(par, ctypes.c_int32), int(n_slots), tptr)
     h = ctypes.c_void_p()
     nbytes = ctypes.c_size_t()
     _check(lib.jt_compile_index_maps(ctypes.byref(d), ctypes.byref(h), ctypes.byref(nbytes)),
@@ -208,7 +225,8 @@ def jt_last_error() -> str:
 class JunctionTreePlan:
     """A compiled tree (host side only): index maps and schedule facts."""
 
-    def __init__(self, card, clique_off, clique_vars, parent, n_slots: int = 1):
+    def __init__(self, card, clique_off, clique_vars, parent, n_slots: int = 1, tuning: Optional[dict] = None):
+        self.tuning = dict(tuning) if tuning else {}
         self.card = np.ascontiguousarray(card, dtype=np.int32)
         self.clique_off = np.ascontiguousarray(clique_off, dtype=np.int64)
         self.clique_vars = np.ascontiguousarray(clique_vars, dtype=np.int32)
@@ -216,15 +234,15 @@ class JunctionTreePlan:
         self.n_cliques = int(self.parent.shape[0])
         self.n_slots = int(n_slots)
         self.handle, self.device_bytes = jt_compile_index_maps(self.card, self.clique_off, self.clique_vars,
-                                                               self.parent, n_slots)
+                                                               self.parent, n_slots, self.tuning)
         self.table_size = np.asarray([jt_query(self.handle, JT_Q_TABLE_SIZE, c) for c in range(self.n_cliques)],
                                      dtype=np.int64)
         self.table_off = np.concatenate([[0], np.cumsum(self.table_size)]).astype(np.int64)
 
     @classmethod
-    def from_instance(cls, inst, n_slots: Optional[int] = None):
+    def from_instance(cls, inst, n_slots: Optional[int] = None, tuning: Optional[dict] = None):
         return cls(inst.card, inst.clique_off, inst.clique_vars, inst.parent,
-                   n_slots if n_slots is not None else max(1, inst.n_slots))
+                   n_slots if n_slots is not None else max(1, inst.n_slots), tuning)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -249,9 +267,9 @@ class JunctionTree(JunctionTreePlan):
     """A compiled tree bound to torch-owned device memory on one stream."""
 
     def __init__(self, card, clique_off, clique_vars, parent, potentials: np.ndarray, n_slots: int = 1,
-                 device: str = "cuda", stream=None):
+                 device: str = "cuda", stream=None, tuning: Optional[dict] = None):
         import torch
-        super().__init__(card, clique_off, clique_vars, parent, n_slots)
+        super().__init__(card, clique_off, clique_vars, parent, n_slots, tuning)
         self.torch = torch
         self.device = torch.device(device)
         # a stream of its own: the legacy default stream cannot be captured

@@ -1,0 +1,72 @@
+"""Autotuner for the shape choices of the fused schedule.
+
+The tile of a clique is fixed by its table layout (the innermost
+cardinalities); what can be chosen per tree is how the work is cut: the size
+of a group (the entries one block reduces into one partial row), the blocks a
+launch aims for, and how many streams the root's subtrees are spread over
+(`jt_tuning` in include/jt.h).  The tuner compiles the tree once per
+candidate, times propagations of the same evidence on the GPU and keeps the
+fastest.  Every candidate computes the same messages; results differ only by
+rounding order and stay within the stated tolerance.
+"""
+from __future__ import annotations
+
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+# Candidates around the built-in defaults (group 8K..32K entries, 1280 blocks
+# per launch): one knob moved at a time, plus two joint moves.  (Lanes are
+# disabled in the library, so max_lanes is not searched.)
+DEFAULT_CANDIDATES: List[Dict[str, int]] = [
+    {},
+    {"group_min": 4096},
+    {"group_min": 16384},
+    {"group_div": 512},
+    {"group_div": 2048},
+    {"target_blocks": 1024},
+    {"target_blocks": 2560},
+    {"group_min": 16384, "target_blocks": 2560},
+    {"group_min": 4096, "target_blocks": 1024},
+]
+
+
+def choose(candidates: Sequence[Dict[str, int]], timer: Callable[[Dict[str, int]], float]
+           ) -> Tuple[Dict[str, int], List[Tuple[Dict[str, int], float]]]:
+    """Time every candidate with `timer` (ms per propagation) and return the
+    fastest (the earliest listed among equals) with the whole table."""
+    table = [(dict(c), float(timer(c))) for c in candidates]
+    best = min(range(len(table)), key=lambda i: (table[i][1], i))
+    return table[best][0], table
+
+
+def gpu_timer(inst, n_slots: Optional[int] = None, mode: str = "graph", steps: int = 10, warmup: int = 2,
+              device: str = "cuda:0") -> Callable[[Dict[str, int]], float]:
+    """ms per propagation of `inst` (its own evidence) for one candidate."""
+    import torch
+
+    from paper_1202_3777_amd import jt
+
+    def run(cand: Dict[str, int]) -> float:
+        tree = jt.JunctionTree.from_instance(inst, n_slots=n_slots, device=device, tuning=cand)
+        for _ in range(warmup):
+            tree.propagate(mode)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(tree.stream)
+        for _ in range(steps):
+            tree.propagate(mode)
+        b.record(tree.stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        del tree
+        torch.cuda.empty_cache()
+        return ms
+
+    return run
+
+
+def autotune(inst, n_slots: Optional[int] = None, candidates: Optional[Sequence[Dict[str, int]]] = None,
+             **timer_kw) -> Tuple[Dict[str, int], List[Tuple[Dict[str, int], float]]]:
+    """Pick the fastest shape choice for `inst` on the GPU."""
+    return choose(candidates if candidates is not None else DEFAULT_CANDIDATES,
+                  gpu_timer(inst, n_slots=n_slots, **timer_kw))

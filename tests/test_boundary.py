@@ -197,5 +197,67 @@ def test_schedule_facts(name, kw):
     # set-up kernel + reset pass, (marginalize-and-finalize, scatter) per
     # message, totals-and-finalize + normalize at the end
     assert plan.query(jt.JT_Q_N_LAUNCHES_PLAIN) == 2 + 2 * 2 * (n - 1) + 2
-    # one pass launch per collect level and per distribute level
-    assert plan.query(jt.JT_Q_N_LAUNCHES_FUSED) == plan.query(jt.JT_Q_HEIGHT) + plan.query(jt.JT_Q_DEPTH)
+    # one pass launch per collect level and per distribute level of every
+    # lane; a lane is a set of whole subtrees of the root, and the root's two
+    # passes run on the bound stream
+    n_lanes = plan.query(jt.JT_Q_N_LANES)
+    nlaunch = plan.query(jt.JT_Q_N_LAUNCHES_FUSED)
+    # the launches' bytes add up to the propagation's; every launch is a pass
+    assert sum(plan.query(jt.JT_Q_FUSED_LAUNCH_BYTES, i) for i in range(nlaunch)) == exp
+    assert all(plan.query(jt.JT_Q_FUSED_LAUNCH_KIND, i) == 1 for i in range(nlaunch))
+    if n_lanes == 0:
+        assert nlaunch == plan.query(jt.JT_Q_HEIGHT) + plan.query(jt.JT_Q_DEPTH)
+        return
+    n = inst.n_cliques
+    lane = [plan.query(jt.JT_Q_CLIQUE_LANE, c) for c in range(n)]
+    assert lane[root] == -1 and all(lane[c] == lane[sparent[c]] for c in range(n) if sparent[c] not in (-1, root))
+    assert sorted(set(lane) - {-1}) == list(range(n_lanes))
+    height = [0] * n
+    depth = [0 if c == root else None for c in range(n)]
+    order = [root]
+    for x in order:
+        for c in range(n):
+            if sparent[c] == x:
+                depth[c] = depth[x] + 1
+                order.append(c)
+    for c in reversed(order):
+        if sparent[c] >= 0:
+            height[sparent[c]] = max(height[sparent[c]], height[c] + 1)
+    launch_lanes = [plan.query(jt.JT_Q_FUSED_LAUNCH_LANE, i) for i in range(nlaunch)]
+    assert launch_lanes.count(-1) == 2
+    for l in range(n_lanes):
+        members = [c for c in range(n) if lane[c] == l]
+        assert launch_lanes.count(l) == len({height[c] for c in members}) + len({depth[c] for c in members})
+
+
+def test_tuning_changes_cuts_not_work():
+    # every shape choice streams the same tables: same entries, same bytes,
+    # its own grouping; bad values are refused
+    inst = make_instance("c2", 2, n_cliques=12)
+    base = jt.JunctionTreePlan.from_instance(inst)
+    for tuning in ({"group_min": 4096}, {"group_max": 65536, "group_div": 256}, {"target_blocks": 300},
+                   {"max_lanes": 1}):
+        p = jt.JunctionTreePlan.from_instance(inst, tuning=tuning)
+        for q in (jt.JT_Q_BYTES_FUSED, jt.JT_Q_BYTES_PLAIN, jt.JT_Q_ENTRIES_PER_SWEEP, jt.JT_Q_ROOT):
+            assert p.query(q) == base.query(q)
+        if tuning.get("max_lanes") == 1:
+            assert p.query(jt.JT_Q_N_LANES) == 0
+            assert p.query(jt.JT_Q_N_LAUNCHES_FUSED) == p.query(jt.JT_Q_HEIGHT) + p.query(jt.JT_Q_DEPTH)
+    # lanes are disabled: asking for more than one is refused
+    for bad in ({"group_min": -1}, {"max_lanes": 9}, {"max_lanes": 2}, {"group_min": 65536, "group_max": 1024}):
+        with pytest.raises(jt.JTError) as ei:
+            jt.JunctionTreePlan.from_instance(inst, tuning=bad)
+        assert ei.value.code == jt.JT_E_ARG
+    with pytest.raises(ValueError):
+        jt.JunctionTreePlan.from_instance(inst, tuning={"tile": 4})
+
+
+def test_autotuner_picks_the_fastest():
+    from paper_1202_3777_amd import tune
+    times = {(): 3.0, (("group_min", 4096),): 2.0, (("target_blocks", 1024),): 2.0}
+    cands = [{}, {"group_min": 4096}, {"target_blocks": 1024}]
+    best, table = tune.choose(cands, lambda c: times[tuple(sorted(c.items()))])
+    assert best == {"group_min": 4096}          # the earliest of the two fastest
+    assert [t for _, t in table] == [3.0, 2.0, 2.0]
+    for c in tune.DEFAULT_CANDIDATES:            # every default candidate compiles
+        jt.JunctionTreePlan.from_instance(make_instance("c1", 0), tuning=c)
