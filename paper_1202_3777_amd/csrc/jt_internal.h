@@ -23,6 +23,7 @@
 #define JT_NG_REG 4               /* gathers whose Jin values live in registers */
 #define JT_LDS_RATIO_FLOATS 8192  /* at most 32 KiB of LDS for staged ratio tables */
 #define JT_FIN_LDS_FLOATS 64      /* smallest dynamic LDS of a pass launch */
+#define JT_FIN_STAGE_FLOATS 4096  /* separators up to this size are finalized through LDS */
 #ifndef JT_FIN_BATCH
 #define JT_FIN_BATCH 16           /* partial loads a finalize thread issues before using them */
 #endif

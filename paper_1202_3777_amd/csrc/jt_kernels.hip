@@ -443,9 +443,10 @@ struct FinPtrs {
     int32_t n_cliques;
 };
 
-// Keep the loads above this point from being moved below it (and the uses
-// below from being moved above): the batch's loads are all in flight before
-// the first one is waited for.
+// Keep the loads above this point from being moved below it and the uses
+// below from being moved above (a volatile asm with a memory clobber bounds
+// the scheduling region).  With the loads of a batch free of branches, they
+// are all in flight before the first one is waited for.
 __device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
 
 // Column sums of the partial rows for columns j = jj + CT*(c0 + c), c < CB,
@@ -453,7 +454,7 @@ __device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
 // (a0 + a1) + (a2 + a3); RB rows per batch, so each batch issues CB*RB loads
 // before any is used.  Writes the sums to raw and returns their FP64 total.
 template <int CB, int RB>
-__device__ __forceinline__ double column_sums(const float *P, float *raw, int ssize, int CT, int R, int jj, int r,
+__device__ __forceinline__ double column_sums(const float *P, float *stage, int ssize, int CT, int R, int jj, int r,
                                               int c0, int ncol, int nrow, float *first) {
     float a[CB][4];
 #pragma unroll
@@ -461,19 +462,25 @@ __device__ __forceinline__ double column_sums(const float *P, float *raw, int ss
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[c][q] = 0.f;
     for (int i0 = 0; i0 < nrow; i0 += RB) {
+        // every load is issued (out-of-range ones read element 0 and are
+        // dropped after the fence): no branch separates the loads, so none
+        // of them waits for another
         float x[CB][RB];
 #pragma unroll
         for (int c = 0; c < CB; ++c)
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
-                x[c][q] = 0.f;
-                if (c0 + c < ncol && i0 + q < nrow) x[c][q] = ldp(P + (int64_t)(r + R * (i0 + q)) * ssize + jj + CT * (c0 + c));
+                const bool ok = c0 + c < ncol && i0 + q < nrow;
+                // 32-bit offset from the uniform base (partial regions stay below 2^31 floats)
+                const uint32_t off = ok ? (uint32_t)((r + R * (i0 + q)) * ssize + jj + CT * (c0 + c)) : 0u;
+                x[c][q] = ldp(P + off);
             }
         issue_fence();
 #pragma unroll
         for (int c = 0; c < CB; ++c)
 #pragma unroll
-            for (int q = 0; q < RB; ++q) a[c][q] += x[c][q];   // row i0 + q, i0 a multiple of 4 or 0
+            for (int q = 0; q < RB; ++q)   // row i0 + q, i0 a multiple of 4 or 0
+                a[c][q] += (c0 + c < ncol && i0 + q < nrow) ? x[c][q] : 0.f;
     }
     double local = 0.0;
 #pragma unroll
@@ -481,7 +488,7 @@ __device__ __forceinline__ double column_sums(const float *P, float *raw, int ss
         const float v = (a[c][0] + a[c][1]) + (a[c][2] + a[c][3]);
         if (c0 + c < ncol) {
             if (R == 1) {
-                if (raw) raw[jj + CT * (c0 + c)] = v;
+                if (stage) stage[jj + CT * (c0 + c)] = v;
                 local += (double)v;
             } else {
                 *first = v;   // one column per thread when R > 1
@@ -503,7 +510,44 @@ __device__ __forceinline__ double column_sums(const float *P, float *raw, int ss
 // The loads that do not depend on the partials (the log-scales the update
 // reads) are issued first; steps 1 and 3 each issue their loads in batches
 // before using them, so the finalize costs a few memory round trips.
-__device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &m, int slot, PassLds &L) {
+// Log-scales a finalize combines (written by earlier launches).
+#ifndef JT_FS_EARLY
+#define JT_FS_EARLY 0   // 1: every block loads them at its start
+#endif
+struct FinScalars {
+    double lc;           // sum of the children's collect log-scales (collect, total)
+    double l0, l1, l2;   // distribute: log Z, collect scale of the target, collect scale of the edge;
+                         // one-at-a-time: scale of the edge, collect scale of the source
+};
+
+__device__ __forceinline__ FinScalars load_fin_scalars(const FinPtrs &F, const JtMsg &m, int slot) {
+    const int nc = F.n_cliques;
+    const double *lam = F.lam + (int64_t)slot * F.lam_stride;
+    FinScalars q{0.0, 0.0, 0.0, 0.0};
+    if (m.kind == JT_MSG_COLLECT || m.kind == JT_MSG_TOTAL) {
+        double s0 = 0.0, s1 = 0.0;   // children in order, two interleaved partial sums
+        int a = 0;
+        for (; a + 1 < m.n_children; a += 2) {
+            s0 += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
+            s1 += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a + 1]];
+        }
+        if (a < m.n_children) s0 += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
+        q.lc = s0 + s1;
+    } else if (m.kind == JT_MSG_DIST) {
+        q.l0 = lam[JT_LAM_LOGZ(nc)];
+        q.l1 = lam[JT_LAM_COLL(nc) + m.to];
+        q.l2 = lam[JT_LAM_SC(nc) + m.edge];
+    } else if (m.kind == JT_MSG_PLAIN) {
+        q.l0 = lam[JT_LAM_SC(nc) + m.edge];
+        q.l1 = lam[JT_LAM_COLL(nc) + m.from];
+    } else if (m.kind == JT_MSG_PLAIN_TOTAL) {
+        q.l1 = lam[JT_LAM_COLL(nc) + m.from];
+    }
+    return q;
+}
+
+__device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &m, const FinScalars &fs, int slot,
+                                                 PassLds &L, float *lds_dyn, int lds_floats) {
     const int tid = threadIdx.x;
     const int lane = tid & (JT_WAVE - 1), wave = tid / JT_WAVE;
     const int nc = F.n_cliques;
@@ -527,24 +571,21 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
     const int ncol = jj < ssize ? (ssize - jj + CT - 1) / CT : 0;
     const int nrow = r < nsplit ? (nsplit - r + R - 1) / R : 0;
 
-    // log-scales the update reads: the children's collect scales (wave 0,
-    // one per lane) and the ones tid 0 combines
-    double lcv = 0.0;
-    if (wave == 0 && (m.kind == JT_MSG_COLLECT || m.kind == JT_MSG_TOTAL))
-        for (int a = lane; a < m.n_children; a += JT_WAVE) lcv += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
-    double l0 = 0.0, l1 = 0.0, l2 = 0.0;
-    if (tid == 0) {
-        if (m.kind == JT_MSG_DIST) {
-            l0 = lam[JT_LAM_LOGZ(nc)];
-            l1 = lam[JT_LAM_COLL(nc) + m.to];
-            l2 = lam[JT_LAM_SC(nc) + m.edge];
-        } else if (m.kind == JT_MSG_PLAIN) {
-            l0 = lam[JT_LAM_SC(nc) + m.edge];
-            l1 = lam[JT_LAM_COLL(nc) + m.from];
-        } else if (m.kind == JT_MSG_PLAIN_TOTAL) {
-            l1 = lam[JT_LAM_COLL(nc) + m.from];
-        }
+    const double l0 = fs.l0, l1 = fs.l1, l2 = fs.l2;
+    // old separator entries of the thread's first columns, in flight with
+    // the partial rows
+    float od[4] = {0.f, 0.f, 0.f, 0.f};
+    if (oldc) {
+        const int nod = R == 1 ? ncol : (r == 0 ? ncol : 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) od[q] = oldc[q < nod ? jj + CT * q : 0];   // unused when q >= nod
     }
+    // column sums are staged in LDS when the separator fits (the block's
+    // reduction rows, or the launch's ratio staging area, free by now), else
+    // in the separator table itself
+    float *stage = raw;
+    if (R == 1 && ssize <= JT_WAVES_PER_BLOCK * JT_TILE_MAX) stage = &L.red[0][0];
+    else if (R == 1 && ssize <= lds_floats) stage = lds_dyn;
 
     // 1. column sums; batch shape by the rows per thread (the shape depends
     //    on the message only, so the order is fixed)
@@ -552,13 +593,13 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
     float first = 0.f;
     for (int c0 = 0; c0 < ncol;) {
         if (nrow <= 1) {
-            local += column_sums<16, 1>(P, raw, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
-            c0 += 16;
+            local += column_sums<8, 1>(P, stage, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
+            c0 += 8;
         } else if (nrow <= 2) {
-            local += column_sums<8, 2>(P, raw, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
+            local += column_sums<8, 2>(P, stage, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
             c0 += 8;
         } else {
-            local += column_sums<4, 4>(P, raw, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
+            local += column_sums<4, 4>(P, stage, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
             c0 += 4;
         }
     }
@@ -574,11 +615,10 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
         first = red[jj];
         local = (r == 0 && jj < ssize) ? (double)first : 0.0;
     }
-    // 2. sigma: wave trees, then the waves in order; the children's
-    //    log-scales in a fixed tree too
+    // 2. sigma: wave trees, then the waves in order
     local = wave_sum_lane0(local);
     if (lane == 0) L.wsum[wave] = local;
-    const double lc = wave == 0 ? wave_sum_lane0(lcv) : 0.0;
+    const double lc = fs.lc;
     __syncthreads();
     if (tid == 0) {
         const double sigma = ((L.wsum[0] + L.wsum[1]) + (L.wsum[2] + L.wsum[3]));
@@ -645,7 +685,7 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
     __syncthreads();
     if (!raw) return;
     const float f = L.f;
-    // 3. rewrite the thread's columns, sixteen at a time (loads before stores)
+    // 3. rewrite the thread's columns, eight at a time (loads before stores)
     auto put = [&](int j, float v, float o) {
         const float nw = v * f;
         if (m.kind == JT_MSG_COLLECT) {
@@ -656,24 +696,21 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
         }
     };
     if (R > 1) {
-        if (r == 0 && jj < ssize) put(jj, first, oldc ? oldc[jj] : 0.f);
+        if (r == 0 && jj < ssize) put(jj, first, od[0]);
         return;
     }
-    for (int q0 = 0; q0 < ncol; q0 += 16) {
-        float v16[16], o16[16];
+    for (int q0 = 0; q0 < ncol; q0 += 8) {
+        float v8[8], o8[8];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            v16[u] = 0.f;
-            o16[u] = 0.f;
-            if (q0 + u < ncol) {
-                v16[u] = raw[jj + CT * (q0 + u)];
-                if (oldc) o16[u] = oldc[jj + CT * (q0 + u)];
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int j = q0 + u < ncol ? jj + CT * (q0 + u) : jj;   // out of range: re-read column jj, unused
+            v8[u] = stage[j];   // this thread's own column sums
+            o8[u] = oldc ? ((q0 == 0 && u < 4) ? od[u & 3] : oldc[j]) : 0.f;
         }
         issue_fence();
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (q0 + u < ncol) put(jj + CT * (q0 + u), v16[u], o16[u]);
+        for (int u = 0; u < 8; ++u)
+            if (q0 + u < ncol) put(jj + CT * (q0 + u), v8[u], o8[u]);
     }
 }
 
@@ -696,34 +733,13 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
     float *__restrict__ scale, float *__restrict__ partial, const JtMsg *__restrict__ msgs,
     const int32_t *__restrict__ child_edges, double *__restrict__ lam, int32_t *__restrict__ flag,
     int32_t *__restrict__ icnt, PassStrides st, int64_t lam_stride, int64_t icnt_stride, int n_cliques,
-    int task_begin, int n_tasks) {
+    int task_begin, int n_tasks, int lds_floats) {
     // staged ratio tables, sized per launch
     extern __shared__ __align__(16) float lds_ratio[];
     __shared__ PassLds L;
     const int slot = blockIdx.x / n_tasks;
     const JtBlock *__restrict__ rec = blocks + task_begin + (blockIdx.x - slot * n_tasks);
     const JtItem it = rec->it;
-    JtTask task;
-    task.item = rec->item;
-    task.g0 = rec->g0;
-    task.g1 = rec->g1;
-    task.pad = 0;
-    if (it.vec == 4)
-        pass_block<4>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
-                      lds_ratio, L);
-    else
-        pass_block<1>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
-                      lds_ratio, L);
-    if (it.msg < 0) return;
-    const JtMsg m = msgs[it.msg];   // in flight while the stores drain
-    int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
-    wait_vm_stores();   // this wave's partials are acknowledged
-    __syncthreads();
-    if (it.n_tasks > 1) {
-        if (threadIdx.x == 0) L.last = (atomicAdd(cnt, 1) == it.n_tasks - 1);
-        __syncthreads();
-        if (!L.last) return;
-    }
     FinPtrs F;
     F.child_edges = child_edges;
     F.partial = partial;
@@ -736,7 +752,41 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
     F.lam_stride = lam_stride;
     F.scale_stride = st.scale;
     F.n_cliques = n_cliques;
-    finalize_message(F, m, slot, L);
+    // the message and the log-scales its finalize reads, loaded now so that
+    // their latency hides under the streaming (only the last block uses them)
+    JtMsg m;
+    FinScalars fs{0.0, 0.0, 0.0, 0.0};
+#if JT_FS_EARLY
+    if (it.msg >= 0) {
+        m = msgs[it.msg];
+        fs = load_fin_scalars(F, m, slot);
+    }
+#endif
+    JtTask task;
+    task.item = rec->item;
+    task.g0 = rec->g0;
+    task.g1 = rec->g1;
+    task.pad = 0;
+    if (it.vec == 4)
+        pass_block<4>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
+                      lds_ratio, L);
+    else
+        pass_block<1>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
+                      lds_ratio, L);
+    if (it.msg < 0) return;
+    int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
+    wait_vm_stores();   // this wave's partials are acknowledged
+    __syncthreads();
+    if (it.n_tasks > 1) {
+        if (threadIdx.x == 0) L.last = (atomicAdd(cnt, 1) == it.n_tasks - 1);
+        __syncthreads();
+        if (!L.last) return;
+    }
+#if !JT_FS_EARLY
+    m = msgs[it.msg];
+    fs = load_fin_scalars(F, m, slot);
+#endif
+    finalize_message(F, m, fs, slot, L, lds_ratio, lds_floats);
     if (it.n_tasks > 1 && threadIdx.x == 0) *cnt = 0;    // ready for the next propagation
 }
 
@@ -764,7 +814,7 @@ hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slo
     hipLaunchKernelGGL(jt_pass_kernel, dim3((unsigned)n_tasks * (unsigned)n_slots), dim3(JT_BLOCK),
                        (size_t)lds_floats * sizeof(float), s, d.blocks, d.gathers, d.meta, d.ev_idx,
                        d.ev_ent, d.init, d.coll, d.out, d.sep, d.scale, d.partial, d.msgs, d.child_edges, d.lam,
-                       d.flag, d.icnt, st, d.lam_stride, d.icnt_stride, d.n_cliques, task_begin, n_tasks);
+                       d.flag, d.icnt, st, d.lam_stride, d.icnt_stride, d.n_cliques, task_begin, n_tasks, lds_floats);
     return hipGetLastError();
 }
 

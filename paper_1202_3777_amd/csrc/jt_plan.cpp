@@ -30,6 +30,9 @@ constexpr int64_t kAlignFloats = 64;       // 256-byte alignment of every table
 #ifndef JT_GROUP_MAX
 #define JT_GROUP_MAX 32768
 #endif
+#ifndef JT_WRITE_WEIGHT
+#define JT_WRITE_WEIGHT 1          // work of a stored entry relative to a read-only one
+#endif
 #ifndef JT_GROUP_DIV
 #define JT_GROUP_DIV 1024
 #endif
@@ -209,14 +212,17 @@ int64_t group_entries_for(const Plan &P, int64_t level_entries) {
 
 // Blocks over the items [i0, i1) of one launch: each block takes
 // consecutive groups of one item, one after the other, so that every block
-// streams about the same number of entries and the launch has about
+// moves about the same number of bytes (entries read, plus entries written
+// when the pass stores its table) and the launch has about
 // `target_blocks` blocks (one round of resident blocks: each block's set-up
 // latency is paid once per launch, not once per small group).  Groups per
 // block change no summation order.
 void emit_tasks(Plan &P, int32_t i0, int32_t i1, int64_t target_blocks) {
     const int64_t tb = std::max<int64_t>(1, target_blocks);
+    // work of an entry: its read, plus its write when the pass stores the table
+    auto weight = [&](int32_t i) { return P.items[i].dst_kind != JT_DST_NONE ? JT_WRITE_WEIGHT : 1; };
     int64_t entries = 0;
-    for (int32_t i = i0; i < i1; ++i) entries += (int64_t)P.items[i].T * P.items[i].n_tiles;
+    for (int32_t i = i0; i < i1; ++i) entries += (int64_t)P.items[i].T * P.items[i].n_tiles * weight(i);
     entries *= P.n_slots;
     // Entries per block, rounded up per item: each item adds at most one
     // partly filled block per slot, which the budget leaves room for.  With
@@ -227,7 +233,7 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1, int64_t target_blocks) {
     const int64_t budget = few ? tb - extra : tb;
     const int64_t target = std::max<int64_t>(P.tune.group_min, few ? (entries + budget - 1) / budget : entries / budget);
     for (int32_t i = i0; i < i1; ++i) {
-        const int64_t ge = (int64_t)P.items[i].tpg * P.items[i].T;   // entries of a full group
+        const int64_t ge = (int64_t)P.items[i].tpg * P.items[i].T * weight(i);   // work of a full group
         const int64_t want = few ? (target + ge - 1) / ge : target / ge;
         const int32_t gpb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(P.items[i].n_groups, want));
         for (int32_t g0 = 0; g0 < P.items[i].n_groups; g0 += gpb) {
@@ -996,8 +1002,13 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         for (Launch &l : *L) {
             if (l.is_pass != 1) continue;
             l.lds_floats = JT_FIN_LDS_FLOATS;
-            for (int32_t t = l.begin; t < l.begin + l.count; ++t)
-                l.lds_floats = std::max<int32_t>(l.lds_floats, P.items[P.tasks[t].item].lds_floats);
+            for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
+                const JtItem &it = P.items[P.tasks[t].item];
+                l.lds_floats = std::max<int32_t>(l.lds_floats, it.lds_floats);
+                // room to stage a finalized separator of up to JT_FIN_STAGE_FLOATS entries
+                if (it.msg >= 0)
+                    l.lds_floats = std::max<int32_t>(l.lds_floats, std::min<int32_t>(JT_FIN_STAGE_FLOATS, it.o_ssize));
+            }
             l.lds_floats = (int32_t)align_up(l.lds_floats, 64);
         }
     for (std::vector<Launch> *L : {&P.fused, &P.plain})
