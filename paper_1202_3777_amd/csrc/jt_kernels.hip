@@ -756,12 +756,12 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
     // their latency hides under the streaming (only the last block uses them)
     JtMsg m;
     FinScalars fs{0.0, 0.0, 0.0, 0.0};
-#if JT_FS_EARLY
     if (it.msg >= 0) {
-        m = msgs[it.msg];
+        m = msgs[it.msg];   // uniform: scalar loads, in flight with the block's set-up
+#if JT_FS_EARLY
         fs = load_fin_scalars(F, m, slot);
-    }
 #endif
+    }
     JtTask task;
     task.item = rec->item;
     task.g0 = rec->g0;
@@ -783,7 +783,6 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
         if (!L.last) return;
     }
 #if !JT_FS_EARLY
-    m = msgs[it.msg];
     fs = load_fin_scalars(F, m, slot);
 #endif
     finalize_message(F, m, fs, slot, L, lds_ratio, lds_floats);
