@@ -18,6 +18,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 # disabled in the library, so max_lanes is not searched.)
 DEFAULT_CANDIDATES: List[Dict[str, int]] = [
     {},
+    {"group_min": 2048},
     {"group_min": 4096},
     {"group_min": 16384},
     {"group_div": 512},
@@ -26,6 +27,7 @@ DEFAULT_CANDIDATES: List[Dict[str, int]] = [
     {"target_blocks": 2560},
     {"group_min": 16384, "target_blocks": 2560},
     {"group_min": 4096, "target_blocks": 1024},
+    {"group_min": 2048, "group_div": 512},
 ]
 
 
