@@ -479,8 +479,8 @@ __device__ __forceinline__ double column_sums(const float *P, float *stage, int 
 #pragma unroll
         for (int c = 0; c < CB; ++c)
 #pragma unroll
-            for (int q = 0; q < RB; ++q)   // row i0 + q, i0 a multiple of 4 or 0
-                a[c][q] += (c0 + c < ncol && i0 + q < nrow) ? x[c][q] : 0.f;
+            for (int q = 0; q < RB; ++q)   // row i0 + q into accumulator (i0 + q) % 4 (RB is 1, 2 or a multiple of 4)
+                a[c][q & 3] += (c0 + c < ncol && i0 + q < nrow) ? x[c][q] : 0.f;
     }
     double local = 0.0;
 #pragma unroll
@@ -525,13 +525,27 @@ __device__ __forceinline__ FinScalars load_fin_scalars(const FinPtrs &F, const J
     const double *lam = F.lam + (int64_t)slot * F.lam_stride;
     FinScalars q{0.0, 0.0, 0.0, 0.0};
     if (m.kind == JT_MSG_COLLECT || m.kind == JT_MSG_TOTAL) {
-        double s0 = 0.0, s1 = 0.0;   // children in order, two interleaved partial sums
-        int a = 0;
-        for (; a + 1 < m.n_children; a += 2) {
-            s0 += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
-            s1 += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a + 1]];
+        // children in order, two interleaved partial sums (even-numbered
+        // children into s0, odd into s1); eight children per batch: their
+        // edge ids, then their log-scales, each batch of loads in flight
+        // together (two round trips per eight children, not two per two)
+        double s0 = 0.0, s1 = 0.0;
+        for (int b = 0; b < m.n_children; b += 8) {
+            int e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = F.child_edges[m.child_base + (b + u < m.n_children ? b + u : b)];
+            issue_fence();
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = lam[JT_LAM_SC(nc) + e[u]];
+            issue_fence();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (b + u >= m.n_children) break;
+                if ((u & 1) == 0) s0 += v[u];
+                else s1 += v[u];
+            }
         }
-        if (a < m.n_children) s0 += lam[JT_LAM_SC(nc) + F.child_edges[m.child_base + a]];
         q.lc = s0 + s1;
     } else if (m.kind == JT_MSG_DIST) {
         q.l0 = lam[JT_LAM_LOGZ(nc)];
@@ -598,6 +612,12 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
         } else if (nrow <= 2) {
             local += column_sums<8, 2>(P, stage, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
             c0 += 8;
+        } else if (ncol - c0 <= 1) {
+            // one column, many rows: 12 rows per batch (a 4 x 4 batch would
+            // leave three of its four columns empty and take three times the
+            // round trips); rows reach the same accumulators in the same order
+            local += column_sums<1, 12>(P, stage, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
+            c0 += 1;
         } else {
             local += column_sums<4, 4>(P, stage, ssize, CT, R, jj, r, c0, ncol, nrow, &first);
             c0 += 4;

@@ -2,6 +2,10 @@
 
     python -m paper_1202_3777_amd.rocprof_summary stats DIR
         per-kernel calls / average / total from a --kernel-trace --stats run
+    python -m paper_1202_3777_amd.rocprof_summary launches DIR --config CFG [--tuning JSON]
+        launch by launch of the last fused propagation in a --kernel-trace run
+        of bench.py: grid, start, duration, FP32 table bytes (from the plan,
+        host only) and the bytes / duration rate
     python -m paper_1202_3777_amd.rocprof_summary traffic --kernel NAME \\
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N \\
         [--launches-per-step K] --out FILE.json
@@ -58,6 +62,25 @@ def stats(d):
              "total_ns": int(float(r["TotalDurationNs"])), "pct": float(r["Percentage"])} for r in rows]
 
 
+def launches(d, config, tuning=None, seed=0, kernel="jt_pass_kernel"):
+    """Rows of the last propagation's launches: (grid blocks, start us, dur us, bytes)."""
+    from paper_1202_3777_amd import jt
+    from paper_1202_3777_amd.instances import make_instance
+    rows = [r for r in _csv(d, "*kernel_trace.csv") if r["Kernel_Name"].startswith(kernel)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    plan = jt.JunctionTreePlan.from_instance(make_instance(config, seed), tuning=tuning)
+    n = plan.query(jt.JT_Q_N_LAUNCHES_FUSED)
+    last = rows[-n:]
+    t0 = int(last[0]["Start_Timestamp"])
+    out = []
+    for i, r in enumerate(last):
+        s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0))) // int(r.get("Workgroup_Size_X", 256) or 256)
+        out.append((grid, (s - t0) / 1e3, (e - s) / 1e3, plan.query(jt.JT_Q_FUSED_LAUNCH_BYTES, i)))
+    span = (int(last[-1]["End_Timestamp"]) - t0) / 1e3
+    return out, span
+
+
 def _match(d, name):
     for k, v in d.items():
         if k.startswith(name):
@@ -96,6 +119,11 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("dir")
+    l = sub.add_parser("launches")
+    l.add_argument("dir")
+    l.add_argument("--config", required=True)
+    l.add_argument("--tuning", default=None)
+    l.add_argument("--seed", type=int, default=0)
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
     t.add_argument("--fetch", required=True)
@@ -110,6 +138,14 @@ def main(argv=None):
         for r in stats(a.dir):
             print(f"{r['name'][:40]:40s} calls {r['calls']:6d} avg {r['avg_ns'] / 1e3:9.2f} us "
                   f"total {r['total_ns'] / 1e6:9.3f} ms {r['pct']:6.2f} %")
+    elif a.cmd == "launches":
+        rows, span = launches(a.dir, a.config, json.loads(a.tuning) if a.tuning else None, a.seed)
+        busy = 0.0
+        for i, (g, st, du, b) in enumerate(rows):
+            busy += du
+            print(f"{i:3d} jt_pass_kernel grid {g:7d} blk start {st:8.1f} dur {du:8.1f} us "
+                  f"{b / 2**20:9.1f} MiB {b / (du * 1e3):7.0f} GB/s")
+        print(f"span {span:.1f} us, kernels busy {busy:.1f} us, gaps {span - busy:.1f} us")
     else:
         traffic(a)
 

@@ -98,6 +98,23 @@ def test_c4_full_batch_sampled():
     run_case(inst, modes=("graph",), slots=[0, 37, 128, 255])
 
 
+def test_autotuner_candidates_full_size():
+    # every shape choice the autotuner may hand to the benchmark: the c4
+    # 256-slot batch (sampled slots) and the c2 tree, each against the oracle
+    jt = _gpu()
+    from paper_1202_3777_amd.tune import DEFAULT_CANDIDATES
+    for cfg, slots in (("c4", [0, 201]), ("c2", [0])):
+        inst = make_instance(cfg, 0)
+        plan = oracle.Plan.from_instance(inst)
+        refs = {s: plan.run(inst.potentials, *inst.evidence[s]) for s in slots}
+        for cand in DEFAULT_CANDIDATES:
+            tree = jt.JunctionTree.from_instance(inst, tuning=cand)
+            tree.propagate("graph")
+            for s in slots:
+                compare(tree, plan, inst, s, refs[s], f"{inst.name}/graph/{cand}")
+            del tree
+
+
 def test_odd_shapes():
     # prime cardinality above the tile limit (one-entry tiles), cardinality 1,
     # cardinality-3 tables (scalar loads), an empty separator, a single-clique
