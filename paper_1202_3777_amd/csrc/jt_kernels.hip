@@ -32,6 +32,7 @@
 #include "jt_internal.h"
 
 namespace {
+typedef float jt_f4 __attribute__((ext_vector_type(4)));
 
 // Wait until this wave's memory operations are acknowledged (vmcnt(0);
 // expcnt and lgkmcnt left open).  Partials are written with agent-coherent
@@ -111,8 +112,22 @@ __device__ __forceinline__ void fold_store(const float *row, const PassLds &L, i
     }
 }
 
+// Streaming (non-temporal) loads and stores of table entries: a table is
+// touched once per pass, so its lines need not stay in L2, and stores that
+// bypass it leave no dirty lines for the end-of-kernel write-back.
+__device__ __forceinline__ jt_f4 ld_nt4(const float *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const jt_f4 *>(p));
+}
+__device__ __forceinline__ void st_nt4(float *p, float a, float b, float c, float d) {
+    const jt_f4 w = {a, b, c, d};
+    __builtin_nontemporal_store(w, reinterpret_cast<jt_f4 *>(p));
+}
+
 // One block's share of a pass: groups [task.g0, task.g1) of item `it`.
-template <int VEC>
+// NT_SRC: the source table is streamed with non-temporal loads; off when the
+// launch reads the shared initial tables for several slots (those stay cached
+// for the other slots).
+template <int VEC, bool NT_SRC>
 __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task, int slot,
                                            const JtGather *__restrict__ gfirst,
                                            const JtGather *__restrict__ gathers, const int32_t *__restrict__ meta,
@@ -207,16 +222,24 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                 const float *base = src + (int64_t)o * T;
                 if (VEC == 4) {
                     if (valid[0]) {
-                        const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
-                        B.x[u][0] = v4.x;
-                        B.x[u][1] = v4.y;
-                        B.x[u][2] = v4.z;
-                        B.x[u][3] = v4.w;
+                        if (NT_SRC) {
+                            const jt_f4 v4 = ld_nt4(base + pos[0]);
+                            B.x[u][0] = v4.x;
+                            B.x[u][1] = v4.y;
+                            B.x[u][2] = v4.z;
+                            B.x[u][3] = v4.w;
+                        } else {
+                            const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
+                            B.x[u][0] = v4.x;
+                            B.x[u][1] = v4.y;
+                            B.x[u][2] = v4.z;
+                            B.x[u][3] = v4.w;
+                        }
                     }
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (valid[q]) B.x[u][q] = base[pos[q]];
+                        if (valid[q]) B.x[u][q] = NT_SRC ? __builtin_nontemporal_load(base + pos[q]) : base[pos[q]];
                 }
             }
         }
@@ -258,11 +281,11 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             if (dst) {
                 float *b = dst + (int64_t)o * T;
                 if (VEC == 4) {
-                    if (valid[0]) *reinterpret_cast<float4 *>(b + pos[0]) = make_float4(v[0], v[1], v[2], v[3]);
+                    if (valid[0]) st_nt4(b + pos[0], v[0], v[1], v[2], v[3]);
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (valid[q]) b[pos[q]] = v[q];
+                        if (valid[q]) __builtin_nontemporal_store(v[q], b + pos[q]);
                 }
             }
 #pragma unroll
@@ -787,12 +810,23 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
     task.g0 = rec->g0;
     task.g1 = rec->g1;
     task.pad = 0;
-    if (it.vec == 4)
-        pass_block<4>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
-                      lds_ratio, L);
-    else
-        pass_block<1>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale, partial, st,
-                      lds_ratio, L);
+    // the shared initial tables stay cached when several slots read them
+    const bool nt_src = it.src_kind != JT_SRC_INIT || gridDim.x == (unsigned)n_tasks;
+    if (it.vec == 4) {
+        if (nt_src)
+            pass_block<4, true>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
+                                partial, st, lds_ratio, L);
+        else
+            pass_block<4, false>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
+                                 partial, st, lds_ratio, L);
+    } else {
+        if (nt_src)
+            pass_block<1, true>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
+                                partial, st, lds_ratio, L);
+        else
+            pass_block<1, false>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
+                                 partial, st, lds_ratio, L);
+    }
     if (it.msg < 0) return;
     int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
     wait_vm_stores();   // this wave's partials are acknowledged
