@@ -26,6 +26,8 @@ DEFAULT_CANDIDATES: List[Dict[str, int]] = [
     {"target_blocks": 1024},
     {"target_blocks": 2560},
     {"target_blocks": 5120},
+    {"target_blocks": 10240},
+    {"target_blocks": 20480},
     {"group_min": 16384, "target_blocks": 2560},
     {"group_min": 4096, "target_blocks": 1024},
     {"group_min": 2048, "group_div": 512},
