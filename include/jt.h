@@ -145,6 +145,13 @@ jt_status jt_set_evidence(jt_tree t, int32_t slot, int32_t n_obs, const int32_t 
  * every table to the initial potentials with the slot's evidence entered,
  * collect to the root, distribute from it.  Asynchronous on the bound
  * stream; idempotent (always restarts from the initial potentials).
+ *   A collect message depends only on the evidence in the subtree it comes
+ *   from, so with several active slots the fused schedules compute the
+ *   evidence-free collect sweep once (in an extra slot region) and each slot
+ *   recomputes only the cliques with some of its evidence below them; the
+ *   others read the shared messages.  This is chosen per propagation when it
+ *   streams fewer table entries, and every slot's results are bit-identical
+ *   either way (and to the same query propagated alone).
  *   mode  JT_MODE_FUSED, JT_MODE_GRAPH, JT_MODE_PLAIN or JT_MODE_DATAFLOW.
  * Errors: JT_E_STATE (not bound), JT_E_ARG (mode), JT_E_HIP (also reported
  * by the next jt_marginal when a dataflow dependency wait gave up). */
@@ -171,6 +178,16 @@ jt_status jt_marginal(jt_tree t, int32_t slot, int32_t clique, float *out, doubl
  * (sum of |phi_X| floats, host or device pointer).  Same errors as
  * jt_marginal. */
 jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z);
+
+/* Asynchronous read-out on the bound stream: the posteriors of slots
+ * [slot0, slot0 + n) packed in clique order, slot after slot
+ * (n * sum |phi_X| floats), and their log Z_e (n doubles, -inf where the
+ * evidence has probability zero; the posteriors of such a slot are
+ * undefined).  Both outputs are device pointers.  Ordered after the last
+ * propagation; a serving loop records an event after it to know when a
+ * query's result is complete.  Errors: JT_E_ARG, JT_E_STATE (a slot not
+ * active in the last propagation), JT_E_HIP. */
+jt_status jt_read_out(jt_tree t, int32_t slot0, int32_t n, float *posteriors, double *log_z);
 
 /* The cluster-separator mapping of Sec. 3.2 in its single-table form (CSM):
  * for edge (child, parent[child]), side 0 = the child's table, side 1 = the
@@ -208,8 +225,16 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *     over, 0 when everything runs on the bound stream),
  *   JT_Q_CLIQUE_LANE (arg = clique: its lane, -1 for the root or without lanes),
  *   JT_Q_FUSED_LAUNCH_LANE (arg = launch index: the lane it runs on, -1 for
- *     the bound stream).
- * Errors: JT_E_ARG. */
+ *     the bound stream),
+ *   JT_Q_BYTES_LAST (FP32 table bytes the last propagation moved: shared
+ *     tables -- initial tables, evidence-free collect tables read by several
+ *     slots -- counted once per launch, every slot's own tables per slot),
+ *   JT_Q_LAST_SHARED (1 when the last propagation computed the evidence-free
+ *     collect messages once and shared them, see jt_propagate),
+ *   JT_Q_LAST_COLLECT_PASSES ((clique, slot) collect passes it ran, the
+ *     evidence-free slot included).
+ * JT_Q_BYTES_LAST, JT_Q_LAST_SHARED and JT_Q_LAST_COLLECT_PASSES return
+ * JT_E_STATE before the first propagation.  Other errors: JT_E_ARG. */
 #define JT_Q_N_SLOTS 0
 #define JT_Q_TOTAL_ENTRIES 1
 #define JT_Q_TABLE_SIZE 2
@@ -229,6 +254,9 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_N_LANES 16
 #define JT_Q_CLIQUE_LANE 17
 #define JT_Q_FUSED_LAUNCH_LANE 18
+#define JT_Q_BYTES_LAST 19
+#define JT_Q_LAST_SHARED 20
+#define JT_Q_LAST_COLLECT_PASSES 21
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and
@@ -244,8 +272,9 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_ms, int32_t *n_pass,
                      int32_t *n_finalize);
 
-/* Release the handle and its host-side objects (captured graphs included).
- * Device memory stays the caller's.  NULL is ignored. */
+/* Release the handle and its host-side objects (captured graphs included),
+ * after the work queued on its bound stream has finished.  Device memory
+ * stays the caller's.  NULL is ignored. */
 void jt_free(jt_tree t);
 
 /* Thread-local text of the last failure on this thread ("" if none). */

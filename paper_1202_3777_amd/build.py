@@ -31,7 +31,7 @@ def _run(cmd):
 
 def sources():
     return [os.path.join(CSRC, s) for s in HOST_SRCS + DEVICE_SRCS] + [
-        os.path.join(CSRC, "jt_internal.h"), os.path.join(CSRC, "jt_plan.h"),
+        os.path.join(CSRC, "jt_internal.h"), os.path.join(CSRC, "jt_plan.h"), os.path.join(CSRC, "jt_api_internal.h"),
         os.path.join(ROOT, "include", "jt.h")]
 
 

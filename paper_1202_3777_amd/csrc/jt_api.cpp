@@ -12,12 +12,16 @@
 #include <vector>
 
 #include "jt.h"
+#include "jt_api_internal.h"
 #include "jt_plan.h"
 
-hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, int lds_floats, hipStream_t s);
+hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, int lds_floats, int flags,
+                          int64_t work_off, int work_idx, int grid, hipStream_t s);
 hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s);
+hipError_t jt_launch_read_out(const JtDev &d, int slot0, int n_slots, int64_t packed_total, float *dst,
+                              double *log_z, hipStream_t s);
 
-namespace {
+namespace jt_detail {
 
 thread_local std::string g_err;
 
@@ -30,29 +34,9 @@ jt_status hip_err(hipError_t e, const char *what) {
     return set_err(JT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-}  // namespace
+}  // namespace jt_detail
 
-struct jt_tree_s {
-    jt::Plan plan;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    hipStream_t stream = nullptr;
-    bool bound = false;
-    bool propagated = false;
-    JtDev dev;
-    std::vector<std::vector<int32_t>> ev_vars, ev_states;
-    std::vector<char> ev_dirty;
-    std::vector<int32_t> ev_idx_host;   // [n_slots][ev_idx_stride]
-    std::vector<JtEv> ev_ent_host;      // [n_slots][ev_ent_stride]
-    // captured graphs of the level launches, keyed by the number of active slots
-    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
-    // lane streams of the fused schedule (default priority, created at bind)
-    std::vector<hipStream_t> lane_stream;
-    std::vector<hipEvent_t> lane_done;
-    hipEvent_t fork_ev = nullptr;
-    int last_mode = -1;
-    int last_n_active = 0;
-};
+using namespace jt_detail;
 
 namespace {
 
@@ -64,34 +48,183 @@ jt_status dataflow_disabled() {
                              "cause not found)");
 }
 
+}  // namespace
+
+namespace jt_detail {
+
 jt_status check_tree(jt_tree t) {
     if (!t) return set_err(JT_E_ARG, "tree handle is NULL");
     return JT_OK;
 }
 
-jt_status upload_evidence(jt_tree t) {
+// ---- staging ---------------------------------------------------------------
+
+hipError_t stage_begin(Staging &S) {
+    S.k ^= 1;
+    S.used = 0;
+    if (S.pending[S.k]) {
+        hipError_t e = hipEventSynchronize(S.done[S.k]);
+        if (e != hipSuccess) return e;
+        S.pending[S.k] = false;
+    }
+    return hipSuccess;
+}
+
+hipError_t stage_put(Staging &S, void *dev, const void *src, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (S.used + n > S.cap) return hipErrorInvalidValue;
+    char *h = S.host[S.k] + S.used;
+    std::memcpy(h, src, n);
+    S.used += (n + 255) / 256 * 256;
+    return hipMemcpyAsync(dev, h, n, hipMemcpyHostToDevice, s);
+}
+
+hipError_t stage_end(Staging &S, hipStream_t s) {
+    hipError_t e = hipEventRecord(S.done[S.k], s);
+    if (e == hipSuccess) S.pending[S.k] = true;
+    return e;
+}
+
+void drop_staging(Staging &S) {
+    for (int k = 0; k < 2; ++k) {
+        if (S.pending[k] && S.done[k]) (void)hipEventSynchronize(S.done[k]);
+        if (S.done[k]) (void)hipEventDestroy(S.done[k]);
+        if (S.host[k]) (void)hipHostFree(S.host[k]);
+        S.host[k] = nullptr;
+        S.done[k] = nullptr;
+        S.pending[k] = false;
+    }
+    S.cap = S.used = 0;
+}
+
+// Device views of a workspace laid out by the plan.
+void fill_dev(const jt::Plan &P, char *base, JtDev &d) {
+    std::memset(&d, 0, sizeof(d));
+    d.meta = reinterpret_cast<const int32_t *>(base + P.off_meta);
+    d.views = reinterpret_cast<const JtView *>(base + P.off_views);
+    d.gathers = reinterpret_cast<const JtGather *>(base + P.off_gathers);
+    d.items = reinterpret_cast<const JtItem *>(base + P.off_items);
+    d.tasks = reinterpret_cast<const JtTask *>(base + P.off_tasks);
+    d.blocks = reinterpret_cast<const JtBlock *>(base + P.off_blocks);
+    d.msgs = reinterpret_cast<const JtMsg *>(base + P.off_msgs);
+    d.child_edges = reinterpret_cast<const int32_t *>(base + P.off_child);
+    d.icnt = reinterpret_cast<int32_t *>(base + P.off_icnt);
+    d.init = reinterpret_cast<const float *>(base + P.off_init);
+    d.coll = reinterpret_cast<float *>(base + P.off_coll);
+    d.out = reinterpret_cast<float *>(base + P.off_out);
+    d.sep = reinterpret_cast<float *>(base + P.off_sep);
+    d.partial = reinterpret_cast<float *>(base + P.off_partial);
+    d.lam = reinterpret_cast<double *>(base + P.off_lam);
+    d.scale = reinterpret_cast<float *>(base + P.off_scale);
+    d.flag = reinterpret_cast<int32_t *>(base + P.off_flag);
+    d.ev_idx = reinterpret_cast<const int32_t *>(base + P.off_ev_idx);
+    d.ev_ent = reinterpret_cast<const JtEv *>(base + P.off_ev_ent);
+    d.csrc = reinterpret_cast<const int32_t *>(base + P.off_csrc);
+    d.work = reinterpret_cast<const JtWork *>(base + P.off_work);
+    d.work_count = reinterpret_cast<const int32_t *>(base + P.off_work_count);
+    d.cltab = reinterpret_cast<const int64_t *>(base + P.off_cltab);
+    d.coll_stride = P.coll_stride;
+    d.out_stride = P.out_stride;
+    d.sep_stride = P.sep_stride;
+    d.partial_stride = P.partial_stride;
+    d.lam_stride = P.lam_stride;
+    d.scale_stride = P.scale_stride;
+    d.ev_idx_stride = P.ev_idx_stride;
+    d.ev_ent_stride = P.ev_ent_stride;
+    d.icnt_stride = P.icnt_stride;
+    d.csrc_stride = P.csrc_stride;
+    d.n_cliques = P.n_cliques;
+    d.n_msgs = (int32_t)P.msgs.size();
+}
+
+// Enqueue the plan's read-only metadata, the initial tables (aligned layout,
+// one copy per clique) and zeroed arrival counters into a workspace.
+hipError_t upload_static(const jt::Plan &P, char *base, const float *init_potentials, hipStream_t s) {
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e = up(P.off_meta, P.meta.data(), P.meta.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(P.off_views, P.views.data(), P.views.size() * sizeof(JtView));
+    if (e == hipSuccess) e = up(P.off_gathers, P.gathers.data(), P.gathers.size() * sizeof(JtGather));
+    if (e == hipSuccess) e = up(P.off_items, P.items.data(), P.items.size() * sizeof(JtItem));
+    if (e == hipSuccess) e = up(P.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(JtTask));
+    if (e == hipSuccess) e = up(P.off_blocks, P.blocks.data(), P.blocks.size() * sizeof(JtBlock));
+    if (e == hipSuccess) e = up(P.off_msgs, P.msgs.data(), P.msgs.size() * sizeof(JtMsg));
+    if (e == hipSuccess) e = up(P.off_child, P.child_edges.data(), P.child_edges.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = up(P.off_cltab, P.cltab.data(), P.cltab.size() * sizeof(int64_t));
+    // pass arrival counters start at zero; the block that finalizes a message
+    // resets its counter, so no clearing is needed between propagations
+    if (e == hipSuccess)
+        e = hipMemsetAsync(base + P.off_icnt, 0, (size_t)P.n_regions * P.icnt_stride * sizeof(int32_t), s);
+    int64_t src_off = 0;
+    for (int32_t c = 0; c < P.n_cliques && e == hipSuccess; ++c) {
+        const jt::CliqueInfo &C = P.cl[c];
+        e = hipMemcpyAsync(base + P.off_init + C.init_off * sizeof(float), init_potentials + src_off,
+                           (size_t)C.size * sizeof(float), hipMemcpyDefault, s);
+        src_off += C.size;
+    }
+    return e;
+}
+
+// Before a propagation over slots [0, n_active): upload the evidence of the
+// slots whose evidence changed and, for a batched tree, the dynamic schedule
+// (collect sources and work lists) when the evidence or n_active changed.
+jt_status prepare(jt_tree t, int n_active, bool fused) {
     const jt::Plan &P = t->plan;
-    const int S = P.n_slots;
-    int lo = S, hi = -1;
-    for (int s = 0; s < S; ++s)
-        if (t->ev_dirty[s]) {
-            jt::evidence_tables(P, t->ev_vars[s], t->ev_states[s], &t->ev_idx_host[(size_t)s * P.ev_idx_stride],
-                                &t->ev_ent_host[(size_t)s * P.ev_ent_stride]);
-            t->ev_dirty[s] = 0;
-            lo = std::min(lo, s);
-            hi = std::max(hi, s);
+    const int R = P.n_regions;
+    int lo = R, hi = -1;
+    for (int r = 0; r < R; ++r)
+        if (t->ev_dirty[r]) {
+            jt::evidence_tables(P, t->ev_vars[r], t->ev_states[r], &t->ev_idx_host[(size_t)r * P.ev_idx_stride],
+                                &t->ev_ent_host[(size_t)r * P.ev_ent_stride]);
+            t->ev_dirty[r] = 0;
+            lo = std::min(lo, r);
+            hi = std::max(hi, r);
         }
-    if (hi < 0) return JT_OK;
-    const size_t n = (size_t)(hi - lo + 1);
-    hipError_t e = hipMemcpyAsync(t->ws + P.off_ev_idx + (size_t)lo * P.ev_idx_stride * sizeof(int32_t),
-                                  &t->ev_idx_host[(size_t)lo * P.ev_idx_stride], n * P.ev_idx_stride * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, t->stream);
+    const bool dyn = P.share && fused && (t->dyn_version != t->ev_version || t->dyn_n_active != n_active);
+    if (hi < 0 && !dyn) return JT_OK;
+    hipError_t e = stage_begin(t->stage);
+    if (e != hipSuccess) return hip_err(e, "staging");
+    if (hi >= 0) {
+        const size_t n = (size_t)(hi - lo + 1);
+        e = stage_put(t->stage, t->ws + P.off_ev_idx + (size_t)lo * P.ev_idx_stride * sizeof(int32_t),
+                      &t->ev_idx_host[(size_t)lo * P.ev_idx_stride], n * P.ev_idx_stride * sizeof(int32_t), t->stream);
+        if (e == hipSuccess)
+            e = stage_put(t->stage, t->ws + P.off_ev_ent + (size_t)lo * P.ev_ent_stride * sizeof(JtEv),
+                          &t->ev_ent_host[(size_t)lo * P.ev_ent_stride], n * P.ev_ent_stride * sizeof(JtEv),
+                          t->stream);
+    }
+    if (e == hipSuccess && dyn) {
+        try {
+            jt::build_dynamic(P, t->ev_vars, n_active, t->dyn);
+        } catch (const std::bad_alloc &) {
+            return set_err(JT_E_NO_MEM, "host allocation failed");
+        }
+        t->dyn_version = t->ev_version;
+        t->dyn_n_active = n_active;
+        e = stage_put(t->stage, t->ws + P.off_csrc, t->dyn.csrc.data(), t->dyn.csrc.size() * sizeof(int32_t),
+                      t->stream);
+        if (e == hipSuccess)
+            e = stage_put(t->stage, t->ws + P.off_work_count, t->dyn.count.data(),
+                          t->dyn.count.size() * sizeof(int32_t), t->stream);
+        if (e == hipSuccess)
+            e = stage_put(t->stage, t->ws + P.off_work, t->dyn.work.data(), t->dyn.work.size() * sizeof(JtWork),
+                          t->stream);
+    }
+    hipError_t e2 = stage_end(t->stage, t->stream);
     if (e != hipSuccess) return hip_err(e, "evidence upload");
-    e = hipMemcpyAsync(t->ws + P.off_ev_ent + (size_t)lo * P.ev_ent_stride * sizeof(JtEv),
-                       &t->ev_ent_host[(size_t)lo * P.ev_ent_stride], n * P.ev_ent_stride * sizeof(JtEv),
-                       hipMemcpyHostToDevice, t->stream);
-    if (e != hipSuccess) return hip_err(e, "evidence upload");
+    if (e2 != hipSuccess) return hip_err(e2, "evidence upload");
     return JT_OK;
+}
+
+// Launch flags: batched fused launches read collect data through the collect
+// sources; initial tables are streamed when a single slot reads them.
+int launch_flags(const jt::Plan &P, const jt::Launch &l, bool fused, int n_active) {
+    int f = 0;
+    if (P.share && fused) f |= JT_PF_SHARE;
+    if (n_active == 1 && !l.listed) f |= JT_PF_NT_INIT;
+    return f;
 }
 
 // Launch list L on the bound stream and, for launches of a lane, on that
@@ -100,12 +233,13 @@ jt_status upload_evidence(jt_tree t) {
 // marked fork_after lets the lanes continue after it, and the bound stream
 // waits for every lane at the end.  Under stream capture this records a
 // graph whose lane branches run side by side.
-jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L, int S) {
+jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, int S, bool fused, hipStream_t stream,
+                  const std::vector<int32_t> *grids) {
     bool lanes = false;
     for (const jt::Launch &l : L) lanes = lanes || l.lane >= 0;
-    if (lanes && t->lane_stream.empty()) return set_err(JT_E_STATE, "lane streams missing");
+    if (lanes && (t->lane_stream.empty() || stream != t->stream)) return set_err(JT_E_STATE, "lane streams missing");
     auto fork = [&]() -> hipError_t {
-        hipError_t e = hipEventRecord(t->fork_ev, t->stream);
+        hipError_t e = hipEventRecord(t->fork_ev, stream);
         for (hipStream_t ls : t->lane_stream)
             if (e == hipSuccess) e = hipStreamWaitEvent(ls, t->fork_ev, 0);
         return e;
@@ -114,7 +248,7 @@ jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L, int S) {
         hipError_t e = hipSuccess;
         for (size_t k = 0; k < t->lane_stream.size() && e == hipSuccess; ++k) {
             e = hipEventRecord(t->lane_done[k], t->lane_stream[k]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(t->stream, t->lane_done[k], 0);
+            if (e == hipSuccess) e = hipStreamWaitEvent(stream, t->lane_done[k], 0);
         }
         return e;
     };
@@ -125,12 +259,19 @@ jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L, int S) {
             e = join();
             if (e != hipSuccess) return hip_err(e, "lane join");
         }
-        hipStream_t s = l.lane >= 0 ? t->lane_stream[l.lane] : t->stream;
+        hipStream_t s = l.lane >= 0 ? t->lane_stream[l.lane] : stream;
         if (l.is_pass == 2) {
-            e = jt_launch_plain_init(t->dev, S, s);
+            e = jt_launch_plain_init(d, S, s);
         } else if (l.count > 0) {
             if ((int64_t)l.count * S > 0x7fffffffLL) return set_err(JT_E_TOO_LARGE, "grid too large");
-            e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, s);
+            int grid = 0;
+            if (l.listed) {
+                if (!grids || l.work_idx >= (int32_t)grids->size()) return set_err(JT_E_STATE, "work lists missing");
+                grid = (*grids)[l.work_idx];
+                if (grid < 1 || grid > l.work_cap) return set_err(JT_E_STATE, "listed grid out of range");
+            }
+            e = jt_launch_pass(d, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, l, fused, S),
+                               l.listed ? l.work_off : -1, l.work_idx, grid, s);
         }
         if (e != hipSuccess) return hip_err(e, "kernel launch");
         if (l.fork_after && lanes) {
@@ -145,6 +286,10 @@ jt_status enqueue(jt_tree t, const std::vector<jt::Launch> &L, int S) {
     return JT_OK;
 }
 
+}  // namespace jt_detail
+
+namespace {
+
 void drop_lanes(jt_tree t) {
     for (hipStream_t s : t->lane_stream)
         if (s) (void)hipStreamDestroy(s);
@@ -156,6 +301,8 @@ void drop_lanes(jt_tree t) {
     t->fork_ev = nullptr;
 }
 
+constexpr size_t kMaxGraphs = 64;
+
 void drop_graph(jt_tree t) {
     for (auto &kv : t->graphs) {
         if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
@@ -164,14 +311,23 @@ void drop_graph(jt_tree t) {
     t->graphs.clear();
 }
 
-// Capture the launches of one propagation once per number of active slots,
-// then replay the graph.
+// Capture the launches of one propagation once per number of active slots
+// (and, for a batched tree, per set of listed grid sizes), then replay the
+// graph.
 jt_status run_graph(jt_tree t, int S) {
-    auto f = t->graphs.find(S);
+    std::vector<int32_t> key{S};
+    if (t->plan.share) key.insert(key.end(), t->dyn.grid.begin(), t->dyn.grid.end());
+    auto f = t->graphs.find(key);
     if (f == t->graphs.end()) {
+        if (t->graphs.size() >= kMaxGraphs) {
+            // bounded cache: let queued replays finish, then start over
+            hipError_t e = hipStreamSynchronize(t->stream);
+            if (e != hipSuccess) return hip_err(e, "stream synchronize");
+            drop_graph(t);
+        }
         hipError_t e = hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_err(e, "begin capture");
-        jt_status rc = enqueue(t, t->plan.fused, S);
+        jt_status rc = enqueue(t, t->dev, t->plan.fused, S, true, t->stream, &t->dyn.grid);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(t->stream, &g);
         if (rc != JT_OK) {
@@ -185,16 +341,29 @@ jt_status run_graph(jt_tree t, int S) {
             (void)hipGraphDestroy(g);
             return hip_err(e, "graph instantiate");
         }
-        f = t->graphs.emplace(S, std::make_pair(g, x)).first;
+        f = t->graphs.emplace(key, std::make_pair(g, x)).first;
     }
     hipError_t e = hipGraphLaunch(f->second.second, t->stream);
     if (e != hipSuccess) return hip_err(e, "graph launch");
     return JT_OK;
 }
 
-template <class T>
-const T *region(const jt_tree t, size_t off) {
-    return reinterpret_cast<const T *>(t->ws + off);
+// Record what the propagation just enqueued moves (FP32 table bytes).
+void note_last(jt_tree t, int mode, int n_active) {
+    const jt::Plan &P = t->plan;
+    if (mode == JT_MODE_PLAIN) {
+        t->last_bytes = P.bytes_plain;
+        t->last_shared = 0;
+        t->last_collect_pairs = 0;
+    } else if (P.share) {
+        t->last_bytes = t->dyn.bytes;
+        t->last_shared = t->dyn.shared;
+        t->last_collect_pairs = t->dyn.collect_pairs;
+    } else {
+        t->last_bytes = P.bytes_fused;
+        t->last_shared = 0;
+        t->last_collect_pairs = (int64_t)P.n_cliques * n_active;
+    }
 }
 
 jt_status read_slot(jt_tree t, int32_t slot, double *log_z, bool *zero) {
@@ -231,11 +400,11 @@ jt_status jt_compile_index_maps(const jt_tree_desc *desc, jt_tree *out, size_t *
             return set_err(rc, err);
         }
         const jt::Plan &P = t->plan;
-        t->ev_vars.assign(P.n_slots, {});
-        t->ev_states.assign(P.n_slots, {});
-        t->ev_dirty.assign(P.n_slots, 1);
-        t->ev_idx_host.assign((size_t)P.n_slots * P.ev_idx_stride, 0);
-        t->ev_ent_host.assign((size_t)P.n_slots * P.ev_ent_stride, JtEv{0, 1, 1, 0});
+        t->ev_vars.assign(P.n_regions, {});
+        t->ev_states.assign(P.n_regions, {});
+        t->ev_dirty.assign(P.n_regions, 1);
+        t->ev_idx_host.assign((size_t)P.n_regions * P.ev_idx_stride, 0);
+        t->ev_ent_host.assign((size_t)P.n_regions * P.ev_ent_stride, JtEv{0, 1, 1, 0});
         *device_bytes = P.total_bytes;
         *out = t;
         g_err.clear();
@@ -254,8 +423,11 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return set_err(JT_E_ARG, "workspace not 256-byte aligned");
     if (bytes < P.total_bytes)
         return set_err(JT_E_NO_MEM, "workspace of " + std::to_string(bytes) + " bytes, need " + std::to_string(P.total_bytes));
+    // work still queued on the previous binding finishes before its objects go
+    if (t->bound && t->stream) (void)hipStreamSynchronize(t->stream);
     drop_graph(t);
     drop_lanes(t);
+    drop_staging(t->stage);
     if (P.n_lanes > 0) {
         hipError_t le = hipEventCreateWithFlags(&t->fork_ev, hipEventDisableTiming);
         for (int32_t k = 0; k < P.n_lanes && le == hipSuccess; ++k) {
@@ -271,68 +443,28 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
             return hip_err(le, "lane streams");
         }
     }
+    {
+        Staging &S = t->stage;
+        S.cap = P.dyn_bytes + 4096;
+        hipError_t se = hipSuccess;
+        for (int k = 0; k < 2 && se == hipSuccess; ++k) {
+            se = hipHostMalloc(reinterpret_cast<void **>(&S.host[k]), S.cap, hipHostMallocDefault);
+            if (se == hipSuccess) se = hipEventCreateWithFlags(&S.done[k], hipEventDisableTiming);
+        }
+        if (se != hipSuccess) {
+            drop_staging(S);
+            return hip_err(se, "pinned staging buffers");
+        }
+    }
     t->ws = static_cast<char *>(workspace);
     t->ws_bytes = bytes;
     t->stream = static_cast<hipStream_t>(hip_stream);
-    hipStream_t s = t->stream;
-    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
-        if (n == 0) return hipSuccess;
-        return hipMemcpyAsync(t->ws + off, src, n, hipMemcpyHostToDevice, s);
-    };
-    hipError_t e = up(P.off_meta, P.meta.data(), P.meta.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = up(P.off_views, P.views.data(), P.views.size() * sizeof(JtView));
-    if (e == hipSuccess) e = up(P.off_gathers, P.gathers.data(), P.gathers.size() * sizeof(JtGather));
-    if (e == hipSuccess) e = up(P.off_items, P.items.data(), P.items.size() * sizeof(JtItem));
-    if (e == hipSuccess) e = up(P.off_tasks, P.tasks.data(), P.tasks.size() * sizeof(JtTask));
-    if (e == hipSuccess) e = up(P.off_blocks, P.blocks.data(), P.blocks.size() * sizeof(JtBlock));
-    if (e == hipSuccess) e = up(P.off_msgs, P.msgs.data(), P.msgs.size() * sizeof(JtMsg));
-    if (e == hipSuccess) e = up(P.off_child, P.child_edges.data(), P.child_edges.size() * sizeof(int32_t));
-    // pass arrival counters start at zero; the block that finalizes a message
-    // resets its counter, so no clearing is needed between propagations
-    if (e == hipSuccess)
-        e = hipMemsetAsync(t->ws + P.off_icnt, 0, (size_t)P.n_slots * P.icnt_stride * sizeof(int32_t), s);
-    // initial tables into the aligned layout, one copy per clique
-    int64_t src_off = 0;
-    for (int32_t c = 0; c < P.n_cliques && e == hipSuccess; ++c) {
-        const jt::CliqueInfo &C = P.cl[c];
-        e = hipMemcpyAsync(t->ws + P.off_init + C.init_off * sizeof(float), init_potentials + src_off,
-                           (size_t)C.size * sizeof(float), hipMemcpyDefault, s);
-        src_off += C.size;
-    }
+    hipError_t e = upload_static(P, t->ws, init_potentials, t->stream);
     if (e != hipSuccess) return hip_err(e, "jt_bind upload");
-    JtDev &d = t->dev;
-    std::memset(&d, 0, sizeof(d));
-    d.meta = region<int32_t>(t, P.off_meta);
-    d.views = region<JtView>(t, P.off_views);
-    d.gathers = region<JtGather>(t, P.off_gathers);
-    d.items = region<JtItem>(t, P.off_items);
-    d.tasks = region<JtTask>(t, P.off_tasks);
-    d.blocks = region<JtBlock>(t, P.off_blocks);
-    d.msgs = region<JtMsg>(t, P.off_msgs);
-    d.child_edges = region<int32_t>(t, P.off_child);
-    d.icnt = reinterpret_cast<int32_t *>(t->ws + P.off_icnt);
-    d.icnt_stride = P.icnt_stride;
-    d.n_msgs = (int32_t)P.msgs.size();
-    d.init = region<float>(t, P.off_init);
-    d.coll = reinterpret_cast<float *>(t->ws + P.off_coll);
-    d.out = reinterpret_cast<float *>(t->ws + P.off_out);
-    d.sep = reinterpret_cast<float *>(t->ws + P.off_sep);
-    d.partial = reinterpret_cast<float *>(t->ws + P.off_partial);
-    d.lam = reinterpret_cast<double *>(t->ws + P.off_lam);
-    d.scale = reinterpret_cast<float *>(t->ws + P.off_scale);
-    d.flag = reinterpret_cast<int32_t *>(t->ws + P.off_flag);
-    d.ev_idx = region<int32_t>(t, P.off_ev_idx);
-    d.ev_ent = region<JtEv>(t, P.off_ev_ent);
-    d.coll_stride = P.coll_stride;
-    d.out_stride = P.out_stride;
-    d.sep_stride = P.sep_stride;
-    d.partial_stride = P.partial_stride;
-    d.lam_stride = P.lam_stride;
-    d.scale_stride = P.scale_stride;
-    d.ev_idx_stride = P.ev_idx_stride;
-    d.ev_ent_stride = P.ev_ent_stride;
-    d.n_cliques = P.n_cliques;
+    fill_dev(P, t->ws, t->dev);
     std::fill(t->ev_dirty.begin(), t->ev_dirty.end(), 1);
+    t->dyn_version = 0;
+    t->dyn_n_active = -1;
     t->bound = true;
     t->propagated = false;
     g_err.clear();
@@ -355,6 +487,7 @@ jt_status jt_set_evidence(jt_tree t, int32_t slot, int32_t n_obs, const int32_t 
     t->ev_vars[slot].assign(vars, vars + n_obs);
     t->ev_states[slot].assign(states, states + n_obs);
     t->ev_dirty[slot] = 1;
+    ++t->ev_version;
     return JT_OK;
 }
 
@@ -365,18 +498,19 @@ jt_status jt_propagate_n(jt_tree t, int32_t mode, int32_t n_active) {
         return set_err(JT_E_ARG, "unknown mode");
     if (n_active < 1 || n_active > t->plan.n_slots) return set_err(JT_E_ARG, "n_active out of range");
     if (mode == JT_MODE_DATAFLOW) return dataflow_disabled();
-    if (jt_status rc = upload_evidence(t)) return rc;
+    if (jt_status rc = prepare(t, n_active, mode != JT_MODE_PLAIN)) return rc;
     jt_status rc = JT_OK;
     if (mode == JT_MODE_FUSED)
-        rc = enqueue(t, t->plan.fused, n_active);
+        rc = enqueue(t, t->dev, t->plan.fused, n_active, true, t->stream, &t->dyn.grid);
     else if (mode == JT_MODE_PLAIN)
-        rc = enqueue(t, t->plan.plain, n_active);
+        rc = enqueue(t, t->dev, t->plan.plain, n_active, false, t->stream, nullptr);
     else
         rc = run_graph(t, n_active);
     if (rc == JT_OK) {
         t->propagated = true;
         t->last_mode = mode;
         t->last_n_active = n_active;
+        note_last(t, mode, n_active);
     }
     return rc;
 }
@@ -427,6 +561,18 @@ jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z) {
         hipError_t e = hipStreamSynchronize(t->stream);
         if (e != hipSuccess) return hip_err(e, "stream synchronize");
     }
+    return JT_OK;
+}
+
+jt_status jt_read_out(jt_tree t, int32_t slot0, int32_t n, float *posteriors, double *log_z) {
+    if (jt_status rc = check_tree(t)) return rc;
+    const jt::Plan &P = t->plan;
+    if (!posteriors || !log_z) return set_err(JT_E_ARG, "NULL output pointer");
+    if (slot0 < 0 || n < 1 || (int64_t)slot0 + n > P.n_slots) return set_err(JT_E_ARG, "slot range out of range");
+    if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+    if (slot0 + n > t->last_n_active) return set_err(JT_E_STATE, "slot was not active in the last propagation");
+    hipError_t e = jt_launch_read_out(t->dev, slot0, n, P.total_entries, posteriors, log_z, t->stream);
+    if (e != hipSuccess) return hip_err(e, "read-out launch");
     return JT_OK;
 }
 
@@ -504,6 +650,18 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
                                                     : live[arg]->bytes;
             break;
         }
+        case JT_Q_BYTES_LAST:
+            if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+            *out = t->last_bytes;
+            break;
+        case JT_Q_LAST_SHARED:
+            if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+            *out = t->last_shared;
+            break;
+        case JT_Q_LAST_COLLECT_PASSES:
+            if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+            *out = t->last_collect_pairs;
+            break;
         default: return set_err(JT_E_ARG, "unknown query");
     }
     return JT_OK;
@@ -515,10 +673,11 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
     if (!t->bound) return set_err(JT_E_STATE, "jt_profile before jt_bind");
     if (mode != JT_MODE_FUSED && mode != JT_MODE_PLAIN && mode != JT_MODE_DATAFLOW)
         return set_err(JT_E_ARG, "profile mode must be fused, plain or dataflow");
-    if (jt_status rc = upload_evidence(t)) return rc;
     if (mode == JT_MODE_DATAFLOW) return dataflow_disabled();
-    const std::vector<jt::Launch> &L = mode == JT_MODE_FUSED ? t->plan.fused : t->plan.plain;
     const int S = t->plan.n_slots;
+    const bool fused = mode == JT_MODE_FUSED;
+    if (jt_status rc = prepare(t, S, fused)) return rc;
+    const std::vector<jt::Launch> &L = fused ? t->plan.fused : t->plan.plain;
     t->last_n_active = S;
     std::vector<hipEvent_t> ev;
     std::vector<int> kind;
@@ -541,8 +700,12 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
         if (e == hipSuccess) {
             if (l.is_pass == 2)
                 e = jt_launch_plain_init(t->dev, S, t->stream);
+            else if (l.listed && (size_t)l.work_idx >= t->dyn.grid.size())
+                e = hipErrorInvalidValue;
             else
-                e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, t->stream);
+                e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, l, fused, S),
+                                   l.listed ? l.work_off : -1, l.work_idx, l.listed ? t->dyn.grid[l.work_idx] : 0,
+                                   t->stream);
         }
         if (e == hipSuccess) e = hipEventRecord(b, t->stream);
         if (e != hipSuccess) {
@@ -575,6 +738,7 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
     if (rc != JT_OK) return rc;
     t->propagated = true;
     t->last_mode = mode;
+    note_last(t, mode, S);
     if (pass_ms) *pass_ms = tp;
     if (finalize_ms) *finalize_ms = tf;
     if (n_pass) *n_pass = np;
@@ -584,8 +748,13 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
 
 void jt_free(jt_tree t) {
     if (!t) return;
+    // let queued work on the bound stream finish before its graphs, lane
+    // streams and staging buffers go (and before the caller may release the
+    // workspace)
+    if (t->bound && t->stream) (void)hipStreamSynchronize(t->stream);
     drop_graph(t);
     drop_lanes(t);
+    drop_staging(t->stage);
     delete t;
 }
 

@@ -62,9 +62,16 @@ typedef struct {
     int32_t ssize;
     int32_t lds_off;  // float offset of its LDS copy, -1 = read from global memory
     int32_t jin_off, jout_off;   // the view's Jin / Jout tables (int32 meta offsets)
+    int32_t src_clique;          // collect message of this (child) clique: read from the slot that
+                                 // holds that clique's collect data (see JtDev::csrc); -1: the
+                                 // launch's own slot (distribute ratios)
 } JtGather;
 
 enum { JT_SRC_INIT = 0, JT_SRC_COLL = 1, JT_SRC_OUT = 2 };
+
+// Launch flags of the pass kernel.
+#define JT_PF_SHARE 1     // collect data are read through the per-slot collect sources
+#define JT_PF_NT_INIT 2   // initial tables are streamed (read by one slot only)
 enum { JT_DST_NONE = -1, JT_DST_COLL = 1, JT_DST_OUT = 2 };
 
 // One streaming pass over one clique table (per slot):
@@ -144,6 +151,12 @@ typedef struct {
 #define JT_LAM_COLL(nc) (2 * (nc))
 #define JT_LAM_LOGZ(nc) (3 * (nc))
 
+// One entry of a listed launch: block-task `task` (relative to the launch's
+// first task) of slot `slot`.
+typedef struct {
+    int32_t task, slot;
+} JtWork;
+
 // Everything a kernel needs, passed by value.
 typedef struct {
     const int32_t *meta;
@@ -165,8 +178,18 @@ typedef struct {
     int32_t *icnt;                 // per-slot arrival counters of the pass items
     const int32_t *ev_idx;
     const JtEv *ev_ent;
+    // Collect source of every (slot, clique): the slot whose collect data
+    // (absorbed table, collect message to the schedule parent, collect
+    // log-scales) hold this clique's.  A clique whose subtree carries none
+    // of the slot's evidence sends the same collect message as with no
+    // evidence at all, so batched trees compute that message once, in an
+    // extra evidence-free slot, and every such slot reads it from there.
+    const int32_t *csrc;
+    const JtWork *work;            // entries of the listed launches
+    const int32_t *work_count;     // entries per listed launch
+    const int64_t *cltab;          // per clique: posterior offset, size, packed offset
     int64_t coll_stride, out_stride, sep_stride, partial_stride;
     int64_t lam_stride, scale_stride, ev_idx_stride, ev_ent_stride;
-    int64_t icnt_stride;
+    int64_t icnt_stride, csrc_stride;
     int32_t n_cliques, n_msgs;
 } JtDev;

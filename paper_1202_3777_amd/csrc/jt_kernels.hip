@@ -132,8 +132,8 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                                            const JtGather *__restrict__ gfirst,
                                            const JtGather *__restrict__ gathers, const int32_t *__restrict__ meta,
                                            const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
-                                           const float *__restrict__ init, float *__restrict__ coll,
-                                           float *__restrict__ out, const float *__restrict__ sep,
+                                           const float *__restrict__ src, float *__restrict__ dst,
+                                           const float *__restrict__ sep, const int32_t *__restrict__ cs_row,
                                            const float *__restrict__ scale_arr, float *__restrict__ partial,
                                            const PassStrides &st, float *__restrict__ lds_ratio, PassLds &L) {
     const int lane = threadIdx.x & (JT_WAVE - 1);
@@ -155,7 +155,13 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     const int ngr = ng < JT_NG_REG ? ng : JT_NG_REG;
     GatherReg gr[JT_NG_REG];
     int jin[JT_NG_REG][4];
-    const float *__restrict__ sep_slot = sep + (int64_t)slot * st.sep;
+    // float offset of a gathered table in `sep` (all slot regions of the
+    // separator area stay below 2^31 floats): a collect message is read from
+    // its sender's collect source, a distribute ratio from this slot
+    auto gather_off = [&](const JtGather &G) -> int32_t {
+        const int32_t gs = (cs_row && G.src_clique >= 0) ? cs_row[G.src_clique] : slot;
+        return gs * (int32_t)st.sep + G.sep_off;
+    };
 #pragma unroll
     for (int g = 0; g < JT_NG_REG; ++g) {
         gr[g].jout_off = 0;
@@ -167,7 +173,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             const JtGather G = gfirst[g];
             gr[g].jout_off = G.jout_off;
             gr[g].in_lds = G.lds_off >= 0;
-            gr[g].off = G.lds_off >= 0 ? G.lds_off : G.sep_off;
+            gr[g].off = G.lds_off >= 0 ? G.lds_off : gather_off(G);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (valid[q]) jin[g][q] = meta[G.jin_off + pos[q]];
@@ -193,14 +199,6 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
 
     // written by the finalize of an earlier launch
     const float scale = it.scale_clique >= 0 ? scale_arr[(int64_t)slot * st.scale + it.scale_clique] : 1.0f;
-    const float *src =
-        (it.src_kind == JT_SRC_INIT ? init
-                                    : (it.src_kind == JT_SRC_COLL ? coll + (int64_t)slot * st.coll
-                                                                  : out + (int64_t)slot * st.out)) +
-        it.src_off;
-    float *dst = nullptr;
-    if (it.dst_kind == JT_DST_COLL) dst = coll + (int64_t)slot * st.coll + it.dst_off;
-    if (it.dst_kind == JT_DST_OUT) dst = out + (int64_t)slot * st.out + it.dst_off;
 
     const bool has_out = it.out_view >= 0;
     const int32_t rout_off = it.o_rout_tile;
@@ -263,17 +261,18 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                         for (int q = 0; q < 4; ++q) v[q] *= lds_ratio[gr[gg].off + jo + jin[gg][q]];
                     } else {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) v[q] *= sep_slot[gr[gg].off + jo + jin[gg][q]];
+                        for (int q = 0; q < 4; ++q) v[q] *= sep[gr[gg].off + jo + jin[gg][q]];
                     }
                 }
             }
             for (int gg = JT_NG_REG; gg < ng; ++gg) {
                 const JtGather G = gathers[it.gather_base + gg];
                 const int jo = meta[G.jout_off + o];
+                const int32_t go = gather_off(G);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int j = jo + (valid[q] ? meta[G.jin_off + pos[q]] : 0);
-                    v[q] *= G.lds_off >= 0 ? lds_ratio[G.lds_off + j] : sep_slot[G.sep_off + j];
+                    v[q] *= G.lds_off >= 0 ? lds_ratio[G.lds_off + j] : sep[go + j];
                 }
             }
 #pragma unroll
@@ -306,7 +305,8 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     auto stage = [&]() {
         for (int gg = 0; gg < it.n_gather_lds; ++gg) {
             const JtGather G = gg < JT_NG_REG ? gfirst[gg] : gathers[it.gather_base + gg];
-            for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = sep_slot[G.sep_off + j];
+            const float *__restrict__ gt = sep + gather_off(G);
+            for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = gt[j];
         }
         if (has_out) {
             for (int t = threadIdx.x; t < T; t += JT_BLOCK) L.perm[t] = meta[it.o_perm + t];
@@ -456,7 +456,8 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
 }
 
 struct FinPtrs {
-    const int32_t *__restrict__ child_edges;
+    const int32_t *__restrict__ child_edges;   // pairs (edge id, child clique)
+    const int32_t *__restrict__ cs_row;        // this slot's collect sources, NULL: the slot itself
     const float *__restrict__ partial;
     float *__restrict__ sep;
     double *__restrict__ lam;
@@ -543,6 +544,12 @@ struct FinScalars {
                          // one-at-a-time: scale of the edge, collect scale of the source
 };
 
+// The slot whose collect data hold clique c's (the evidence-free slot when c
+// has no evidence of this slot below it).
+__device__ __forceinline__ int64_t coll_slot(const int32_t *__restrict__ cs_row, int c, int slot) {
+    return cs_row ? (int64_t)cs_row[c] : (int64_t)slot;
+}
+
 __device__ __forceinline__ FinScalars load_fin_scalars(const FinPtrs &F, const JtMsg &m, int slot) {
     const int nc = F.n_cliques;
     const double *lam = F.lam + (int64_t)slot * F.lam_stride;
@@ -550,17 +557,25 @@ __device__ __forceinline__ FinScalars load_fin_scalars(const FinPtrs &F, const J
     if (m.kind == JT_MSG_COLLECT || m.kind == JT_MSG_TOTAL) {
         // children in order, two interleaved partial sums (even-numbered
         // children into s0, odd into s1); eight children per batch: their
-        // edge ids, then their log-scales, each batch of loads in flight
-        // together (two round trips per eight children, not two per two)
+        // edge ids and cliques, then their log-scales (from each child's
+        // collect source), each batch of loads in flight together
         double s0 = 0.0, s1 = 0.0;
         for (int b = 0; b < m.n_children; b += 8) {
-            int e[8];
+            int e[8], ch[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) e[u] = F.child_edges[m.child_base + (b + u < m.n_children ? b + u : b)];
+            for (int u = 0; u < 8; ++u) {
+                const int k = m.child_base + (b + u < m.n_children ? b + u : b);
+                e[u] = F.child_edges[2 * k];
+                ch[u] = F.child_edges[2 * k + 1];
+            }
+            issue_fence();
+            int64_t cs[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cs[u] = coll_slot(F.cs_row, ch[u], slot);
             issue_fence();
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = lam[JT_LAM_SC(nc) + e[u]];
+            for (int u = 0; u < 8; ++u) v[u] = F.lam[cs[u] * F.lam_stride + JT_LAM_SC(nc) + e[u]];
             issue_fence();
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -571,9 +586,12 @@ __device__ __forceinline__ FinScalars load_fin_scalars(const FinPtrs &F, const J
         }
         q.lc = s0 + s1;
     } else if (m.kind == JT_MSG_DIST) {
+        // the target's collect scale and the collect message's scale belong
+        // to the target's collect source
+        const double *lt = F.lam + coll_slot(F.cs_row, m.to, slot) * F.lam_stride;
         q.l0 = lam[JT_LAM_LOGZ(nc)];
-        q.l1 = lam[JT_LAM_COLL(nc) + m.to];
-        q.l2 = lam[JT_LAM_SC(nc) + m.edge];
+        q.l1 = lt[JT_LAM_COLL(nc) + m.to];
+        q.l2 = lt[JT_LAM_SC(nc) + m.edge];
     } else if (m.kind == JT_MSG_PLAIN) {
         q.l0 = lam[JT_LAM_SC(nc) + m.edge];
         q.l1 = lam[JT_LAM_COLL(nc) + m.from];
@@ -596,7 +614,10 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
     float *raw = nullptr;
     if (m.kind == JT_MSG_COLLECT) raw = sep + m.sepc_off;
     if (m.kind == JT_MSG_DIST || m.kind == JT_MSG_PLAIN) raw = sep + m.sepd_off;
-    float *oldc = (m.kind == JT_MSG_DIST || m.kind == JT_MSG_PLAIN) ? sep + m.sepc_off : nullptr;
+    // the old table of a distribute message is the target's collect message
+    float *oldc = nullptr;
+    if (m.kind == JT_MSG_DIST) oldc = F.sep + coll_slot(F.cs_row, m.to, slot) * F.sep_stride + m.sepc_off;
+    if (m.kind == JT_MSG_PLAIN) oldc = sep + m.sepc_off;
 
     int CT = JT_BLOCK;
     if (ssize < JT_BLOCK) {
@@ -769,78 +790,141 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
 // block that arrives last sums all partial rows (fixed order), forms sigma,
 // the log-scales and the new table or ratio.  No block ever waits for
 // another, and the next level's launch sees finished messages.
-extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_pass_kernel(
+//
+// Work: a plain launch has n_tasks blocks per slot (block b: slot b / n_tasks,
+// task b % n_tasks).  A listed launch reads its (task, slot) entries from
+// `work`, one per block; its grid is at least the entry count (*work_count)
+// and the blocks beyond it return at once.
+// Five waves per SIMD (five blocks per CU): the register budget that keeps
+// enough tile loads in flight per CU (measured: 4 waves per SIMD costs 5 % on
+// the large-clique tree and 10 % on the batched one).
+extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_per_eu(5, 8))) void jt_pass_kernel(
     const JtBlock *__restrict__ blocks, const JtGather *__restrict__ gathers,
     const int32_t *__restrict__ meta, const int32_t *__restrict__ ev_idx, const JtEv *__restrict__ ev_ent,
     const float *__restrict__ init, float *__restrict__ coll, float *__restrict__ out, float *__restrict__ sep,
     float *__restrict__ scale, float *__restrict__ partial, const JtMsg *__restrict__ msgs,
     const int32_t *__restrict__ child_edges, double *__restrict__ lam, int32_t *__restrict__ flag,
-    int32_t *__restrict__ icnt, PassStrides st, int64_t lam_stride, int64_t icnt_stride, int n_cliques,
-    int task_begin, int n_tasks, int lds_floats) {
+    int32_t *__restrict__ icnt, const int32_t *__restrict__ csrc, const JtWork *__restrict__ work,
+    const int32_t *__restrict__ work_count, PassStrides st, int64_t lam_stride, int64_t icnt_stride,
+    int64_t csrc_stride, int n_cliques, int task_begin, int n_tasks, int n_plain, int lds_floats, int flags) {
     // staged ratio tables, sized per launch
     extern __shared__ __align__(16) float lds_ratio[];
     __shared__ PassLds L;
-    const int slot = blockIdx.x / n_tasks;
-    const JtBlock *__restrict__ rec = blocks + task_begin + (blockIdx.x - slot * n_tasks);
-    const JtItem it = rec->it;
-    FinPtrs F;
-    F.child_edges = child_edges;
-    F.partial = partial;
-    F.sep = sep;
-    F.lam = lam;
-    F.scale = scale;
-    F.flag = flag;
-    F.partial_stride = st.partial;
-    F.sep_stride = st.sep;
-    F.lam_stride = lam_stride;
-    F.scale_stride = st.scale;
-    F.n_cliques = n_cliques;
-    // the message and the log-scales its finalize reads, loaded now so that
-    // their latency hides under the streaming (only the last block uses them)
-    JtMsg m;
-    FinScalars fs{0.0, 0.0, 0.0, 0.0};
-    if (it.msg >= 0) {
-        m = msgs[it.msg];   // uniform: scalar loads, in flight with the block's set-up
+    {
+        const int w = blockIdx.x;
+        int slot, tix;
+        if (work) {
+            // the entry is read together with the count (the list holds
+            // work_cap entries, so the read stays inside it either way)
+            const JtWork e = work[w];
+            if (w >= *work_count) return;
+            tix = e.task;
+            slot = e.slot;
+        } else {
+            if (w >= n_plain) return;
+            slot = w / n_tasks;
+            tix = w - slot * n_tasks;
+        }
+        const JtBlock *__restrict__ rec = blocks + task_begin + tix;
+        const JtItem it = rec->it;
+        const int32_t *__restrict__ cs_row = (flags & JT_PF_SHARE) ? csrc + (int64_t)slot * csrc_stride : nullptr;
+        FinPtrs F;
+        F.child_edges = child_edges;
+        F.cs_row = cs_row;
+        F.partial = partial;
+        F.sep = sep;
+        F.lam = lam;
+        F.scale = scale;
+        F.flag = flag;
+        F.partial_stride = st.partial;
+        F.sep_stride = st.sep;
+        F.lam_stride = lam_stride;
+        F.scale_stride = st.scale;
+        F.n_cliques = n_cliques;
+        // the message and the log-scales its finalize reads, loaded now so that
+        // their latency hides under the streaming (only the last block uses them)
+        JtMsg m;
+        FinScalars fs{0.0, 0.0, 0.0, 0.0};
+        if (it.msg >= 0) {
+            m = msgs[it.msg];   // uniform: scalar loads, in flight with the block's set-up
 #if JT_FS_EARLY
-        fs = load_fin_scalars(F, m, slot);
+            fs = load_fin_scalars(F, m, slot);
 #endif
-    }
-    JtTask task;
-    task.item = rec->item;
-    task.g0 = rec->g0;
-    task.g1 = rec->g1;
-    task.pad = 0;
-    // the shared initial tables stay cached when several slots read them
-    const bool nt_src = it.src_kind != JT_SRC_INIT || gridDim.x == (unsigned)n_tasks;
-    if (it.vec == 4) {
-        if (nt_src)
-            pass_block<4, true>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
-                                partial, st, lds_ratio, L);
-        else
-            pass_block<4, false>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
-                                 partial, st, lds_ratio, L);
-    } else {
-        if (nt_src)
-            pass_block<1, true>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
-                                partial, st, lds_ratio, L);
-        else
-            pass_block<1, false>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, init, coll, out, sep, scale,
-                                 partial, st, lds_ratio, L);
-    }
-    if (it.msg < 0) return;
-    int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
-    wait_vm_stores();   // this wave's partials are acknowledged
-    __syncthreads();
-    if (it.n_tasks > 1) {
-        if (threadIdx.x == 0) L.last = (atomicAdd(cnt, 1) == it.n_tasks - 1);
-        __syncthreads();
-        if (!L.last) return;
-    }
+        }
+        JtTask task;
+        task.item = rec->item;
+        task.g0 = rec->g0;
+        task.g1 = rec->g1;
+        task.pad = 0;
+        // source and destination tables of this slot; an absorbed collect
+        // table is read from the clique's collect source
+        const float *src;
+        bool shared_src;
+        if (it.src_kind == JT_SRC_INIT) {
+            src = init + it.src_off;
+            shared_src = !(flags & JT_PF_NT_INIT);
+        } else if (it.src_kind == JT_SRC_COLL) {
+            const int64_t cs = coll_slot(cs_row, it.clique, slot);
+            src = coll + cs * st.coll + it.src_off;
+            shared_src = cs != slot;
+        } else {
+            src = out + (int64_t)slot * st.out + it.src_off;
+            shared_src = false;
+        }
+        float *dst = nullptr;
+        if (it.dst_kind == JT_DST_COLL) dst = coll + (int64_t)slot * st.coll + it.dst_off;
+        if (it.dst_kind == JT_DST_OUT) dst = out + (int64_t)slot * st.out + it.dst_off;
+        // a table read by one slot is streamed (non-temporal loads); one that
+        // several slots read stays cached for the others
+        if (it.vec == 4) {
+            if (!shared_src)
+                pass_block<4, true>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row,
+                                    scale, partial, st, lds_ratio, L);
+            else
+                pass_block<4, false>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row,
+                                     scale, partial, st, lds_ratio, L);
+        } else {
+            if (!shared_src)
+                pass_block<1, true>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row,
+                                    scale, partial, st, lds_ratio, L);
+            else
+                pass_block<1, false>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row,
+                                     scale, partial, st, lds_ratio, L);
+        }
+        if (it.msg >= 0) {
+            int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
+            // Hand-off to the finalizing block, ordered by the hardware:
+            //  1. partial rows are stored with agent-scope atomic stores, which
+            //     on gfx950 write through the XCD's L2 to the device-coherent
+            //     level (no dirty copy stays in a cache another XCD cannot see);
+            //  2. every wave waits until its stores are acknowledged (vmcnt 0:
+            //     the write has reached that level) before the barrier;
+            //  3. thread 0 then counts the block's arrival with a device atomic,
+            //     performed at that same level, so the count can only reach
+            //     n_tasks after every block's rows are there;
+            //  4. the last block's loads of the rows are issued after its atomic
+            //     returned (barrier, branch on the result) and are agent-scope
+            //     atomic loads, which bypass the non-coherent caches.
+            // An acquire-release count (L2 write-back per block, L2 invalidate in
+            // the last) gives the same results at a measured 1.6x the time of a
+            // propagation, so the count stays relaxed.
+            wait_vm_stores();
+            __syncthreads();
+            bool last = true;
+            if (it.n_tasks > 1) {
+                if (threadIdx.x == 0) L.last = atomicAdd(cnt, 1) == it.n_tasks - 1;
+                __syncthreads();
+                last = L.last;
+            }
+            if (last) {
 #if !JT_FS_EARLY
-    fs = load_fin_scalars(F, m, slot);
+                fs = load_fin_scalars(F, m, slot);
 #endif
-    finalize_message(F, m, fs, slot, L, lds_ratio, lds_floats);
-    if (it.n_tasks > 1 && threadIdx.x == 0) *cnt = 0;    // ready for the next propagation
+                finalize_message(F, m, fs, slot, L, lds_ratio, lds_floats);
+                if (it.n_tasks > 1 && threadIdx.x == 0) *cnt = 0;    // ready for the next propagation
+            }
+        }
+    }
 }
 
 // One-at-a-time schedule set-up: every separator table := 1, log-scales := 0.
@@ -855,7 +939,11 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_plain_init_kernel(JtDe
 // ---------------------------------------------------------------------------
 // host-side launchers (the C ABI lives in jt_api.cpp)
 
-hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, int lds_floats, hipStream_t s) {
+// A plain launch: n_tasks blocks for each of n_slots slots.  A listed launch
+// (work_off >= 0): `grid` blocks, at least the count d.work_count[work_idx]
+// of entries d.work[work_off ..] and at most the list's capacity.
+hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, int lds_floats, int flags,
+                          int64_t work_off, int work_idx, int grid, hipStream_t s) {
     PassStrides st;
     st.coll = d.coll_stride;
     st.out = d.out_stride;
@@ -864,14 +952,50 @@ hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slo
     st.scale = d.scale_stride;
     st.ev_idx = d.ev_idx_stride;
     st.ev_ent = d.ev_ent_stride;
-    hipLaunchKernelGGL(jt_pass_kernel, dim3((unsigned)n_tasks * (unsigned)n_slots), dim3(JT_BLOCK),
-                       (size_t)lds_floats * sizeof(float), s, d.blocks, d.gathers, d.meta, d.ev_idx,
-                       d.ev_ent, d.init, d.coll, d.out, d.sep, d.scale, d.partial, d.msgs, d.child_edges, d.lam,
-                       d.flag, d.icnt, st, d.lam_stride, d.icnt_stride, d.n_cliques, task_begin, n_tasks, lds_floats);
+    const bool listed = work_off >= 0;
+    const unsigned blocks = listed ? (unsigned)grid : (unsigned)n_tasks * (unsigned)n_slots;
+    hipLaunchKernelGGL(jt_pass_kernel, dim3(blocks), dim3(JT_BLOCK), (size_t)lds_floats * sizeof(float), s, d.blocks,
+                       d.gathers, d.meta, d.ev_idx, d.ev_ent, d.init, d.coll, d.out, d.sep, d.scale, d.partial, d.msgs,
+                       d.child_edges, d.lam, d.flag, d.icnt, d.csrc, listed ? d.work + work_off : nullptr,
+                       listed ? d.work_count + work_idx : nullptr, st, d.lam_stride, d.icnt_stride, d.csrc_stride,
+                       d.n_cliques, task_begin, n_tasks, n_tasks * n_slots, lds_floats, flags);
     return hipGetLastError();
 }
 
 hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s) {
     hipLaunchKernelGGL(jt_plain_init_kernel, dim3((unsigned)n_slots), dim3(JT_BLOCK), 0, s, d);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Read-out (Sec. 2.1: posteriors from the calibrated tables): the posteriors
+// of slots [slot0, slot0 + n) packed in clique order, slot after slot, and
+// their log Z (-inf when the evidence has probability zero).  Block
+// (slot, clique) copies one table, float4 at a time when both ends allow.
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_read_out_kernel(
+    const float *__restrict__ out, int64_t out_stride, const int64_t *__restrict__ cltab, int n_cliques,
+    int slot0, int64_t packed_total, const double *__restrict__ lam, int64_t lam_stride,
+    const int32_t *__restrict__ flag, float *__restrict__ dst, double *__restrict__ log_z) {
+    const int k = blockIdx.x / n_cliques, c = blockIdx.x - k * n_cliques;
+    const int slot = slot0 + k;
+    const int64_t off = cltab[3 * c], n = cltab[3 * c + 1], po = cltab[3 * c + 2];
+    const float *__restrict__ a = out + (int64_t)slot * out_stride + off;
+    float *__restrict__ b = dst + (int64_t)k * packed_total + po;
+    if ((reinterpret_cast<uintptr_t>(b) & 15) == 0 && (n & 3) == 0) {
+        const float4 *__restrict__ a4 = reinterpret_cast<const float4 *>(a);
+        float4 *__restrict__ b4 = reinterpret_cast<float4 *>(b);
+        for (int64_t i = threadIdx.x; i < n / 4; i += JT_BLOCK) b4[i] = a4[i];
+    } else {
+        for (int64_t i = threadIdx.x; i < n; i += JT_BLOCK) b[i] = a[i];
+    }
+    if (c == 0 && threadIdx.x == 0)
+        log_z[k] = flag[slot] ? -INFINITY : lam[(int64_t)slot * lam_stride + JT_LAM_LOGZ(n_cliques)];
+}
+
+hipError_t jt_launch_read_out(const JtDev &d, int slot0, int n_slots, int64_t packed_total, float *dst,
+                              double *log_z, hipStream_t s) {
+    hipLaunchKernelGGL(jt_read_out_kernel, dim3((unsigned)(n_slots * d.n_cliques)), dim3(JT_BLOCK), 0, s, d.out,
+                       d.out_stride, d.cltab, d.n_cliques, slot0, packed_total, d.lam, d.lam_stride, d.flag, dst,
+                       log_z);
     return hipGetLastError();
 }

@@ -274,6 +274,10 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         G.ssize = (int32_t)E.ssize;
         G.jin_off = (int32_t)P.views[G.view].jin_off;
         G.jout_off = (int32_t)P.views[G.view].jout_off;
+        // a collect message is read through the collect source of the clique
+        // that sent it (the edge's other end); a distribute ratio belongs to
+        // the launch's slot
+        G.src_clique = g.dist ? -1 : (c == g.edge ? P.parent[g.edge] : g.edge);
         if (lds_open && lds + E.ssize <= JT_LDS_RATIO_FLOATS) {
             G.lds_off = lds;
             lds += (int32_t)E.ssize;
@@ -405,6 +409,7 @@ bool verify_plan(const Plan &P, std::string &why) {
                 return bad("gather tables");
             if (G.sep_off < 0 || G.sep_off + (int64_t)G.ssize > P.sep_stride) return bad("gather separator range");
             if ((g < it.n_gather_lds) != (G.lds_off >= 0)) return bad("gather LDS order");
+            if (G.src_clique < -1 || G.src_clique >= P.n_cliques) return bad("gather source clique");
             if (G.lds_off >= 0 && G.lds_off + G.ssize > it.lds_floats) return bad("gather LDS range");
         }
         if (it.scale_clique >= P.n_cliques) return bad("scale clique");
@@ -456,6 +461,19 @@ bool verify_plan(const Plan &P, std::string &why) {
             if (std::memcmp(&b.g[g], &P.gathers[b.it.gather_base + g], sizeof(JtGather)) != 0)
                 return bad("block gather copy");
     }
+    {
+        int64_t wt = 0;
+        int32_t nl = 0;
+        for (const Launch &l : P.fused) {
+            if (!l.listed) continue;
+            if (!P.share || !l.collect) return bad("listed launch outside a batched collect");
+            if (l.work_off != wt || l.work_cap != (int64_t)l.count * P.n_regions || l.work_idx != nl)
+                return bad("listed launch layout");
+            wt += l.work_cap;
+            ++nl;
+        }
+        if (wt != P.work_total || nl != P.n_listed) return bad("work totals");
+    }
     for (const JtMsg &m : P.msgs) {
         if (m.ssize < 1 || m.nsplit < 1) return bad("message shape");
         if (m.partial_off < 0 || m.partial_off + (int64_t)m.nsplit * m.ssize > P.partial_stride) return bad("message partial");
@@ -467,7 +485,12 @@ bool verify_plan(const Plan &P, std::string &why) {
                 return bad("message separator range");
             if (m.to < 0 || m.to >= P.n_cliques) return bad("message target");
         }
-        if (m.child_base < 0 || m.child_base + m.n_children > (int32_t)P.child_edges.size()) return bad("children range");
+        if (m.child_base < 0 || 2 * ((int64_t)m.child_base + m.n_children) > (int64_t)P.child_edges.size())
+            return bad("children range");
+        for (int32_t k = 0; k < m.n_children; ++k) {
+            const int32_t e = P.child_edges[2 * (m.child_base + k)], ch = P.child_edges[2 * (m.child_base + k) + 1];
+            if (e < 0 || e >= P.n_cliques || ch < 0 || ch >= P.n_cliques || P.iedge[ch] != e) return bad("child pair");
+        }
     }
     for (const std::vector<Launch> *L : {&P.fused, &P.plain})
         for (const Launch &l : *L) {
@@ -529,6 +552,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.n_vars = nv;
     P.n_cliques = nc;
     P.n_slots = desc->n_slots;
+    P.share = P.n_slots >= 2 ? 1 : 0;
+    P.n_regions = P.n_slots + P.share;
     P.card.assign(desc->card, desc->card + nv);
     P.parent.assign(desc->parent, desc->parent + nc);
     for (int32_t v = 0; v < nv; ++v)
@@ -823,9 +848,12 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             m.ssize = (int32_t)ss;
             m.nsplit = P.items[it].nsplit;
             m.partial_off = poff;
-            m.child_base = (int32_t)P.child_edges.size();
+            m.child_base = (int32_t)P.child_edges.size() / 2;
             m.n_children = (int32_t)C.children.size();
-            for (int32_t ch : C.children) P.child_edges.push_back(P.iedge[ch]);
+            for (int32_t ch : C.children) {
+                P.child_edges.push_back(P.iedge[ch]);
+                P.child_edges.push_back(ch);
+            }
             m.sepc_off = is_root ? 0 : P.edge[P.iedge[c]].sepc_off;
             m.sepd_off = is_root ? 0 : P.edge[P.iedge[c]].sepd_off;
             level_msgs.push_back(m);
@@ -834,6 +862,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         for (const JtMsg &m : level_msgs) P.msgs.push_back(m);
         // the root's collect pass first joins every lane
         push_launch(t0, (int32_t)li - 1, li == 0 && P.n_lanes > 0 ? 1 : 0, 0);
+        P.fused.back().collect = 1;
         }
     }
     for (int32_t d = 0; d <= P.depth; ++d) {
@@ -892,6 +921,20 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         }
     }
     P.bytes_fused = bytes;
+    // batched trees: the collect launches walk per-propagation work lists
+    // (the evidence-free slot's tasks plus the (task, slot) pairs whose
+    // clique has evidence below it), sized for every task of every region
+    if (P.share) {
+        for (Launch &l : P.fused) {
+            if (!l.collect || l.count == 0) continue;
+            l.listed = 1;
+            l.work_off = P.work_total;
+            l.work_cap = (int32_t)std::min<int64_t>((int64_t)l.count * P.n_regions, std::numeric_limits<int32_t>::max());
+            if ((int64_t)l.count * P.n_regions > l.work_cap) return fail(err, JT_E_TOO_LARGE, "work list too long");
+            l.work_idx = P.n_listed++;
+            P.work_total += l.work_cap;
+        }
+    }
 
     // Tables live in the output region and are updated in place.
     bytes = 0;
@@ -1052,7 +1095,18 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         off = (size_t)align_up((int64_t)(off + bytes_), 256);
         return o;
     };
-    const size_t S = (size_t)P.n_slots;
+    const size_t S = (size_t)P.n_regions;   // slot regions, the evidence-free one included
+    P.csrc_stride = align_up(nc, kAlignFloats);
+    P.cltab.assign(3 * (size_t)nc, 0);
+    {
+        int64_t packed = 0;
+        for (int32_t c = 0; c < nc; ++c) {
+            P.cltab[3 * c] = P.cl[c].out_off;
+            P.cltab[3 * c + 1] = P.cl[c].size;
+            P.cltab[3 * c + 2] = packed;
+            packed += P.cl[c].size;
+        }
+    }
     P.off_meta = region(P.meta.size() * sizeof(int32_t));
     P.off_views = region(P.views.size() * sizeof(JtView));
     P.off_gathers = region(std::max<size_t>(1, P.gathers.size()) * sizeof(JtGather));
@@ -1064,6 +1118,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_init = region((size_t)P.init_floats * sizeof(float));
     P.off_coll = region(S * (size_t)P.coll_stride * sizeof(float));
     P.off_out = region(S * (size_t)P.out_stride * sizeof(float));
+    if ((int64_t)S * P.sep_stride > std::numeric_limits<int32_t>::max())
+        return fail(err, JT_E_TOO_LARGE, "separator tables of all slots exceed 2^31 floats");
     P.off_sep = region(S * (size_t)P.sep_stride * sizeof(float));
     P.off_partial = region(S * (size_t)P.partial_stride * sizeof(float));
     P.off_lam = region(S * (size_t)P.lam_stride * sizeof(double));
@@ -1071,17 +1127,112 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_flag = region(S * sizeof(int32_t));
     P.off_ev_idx = region(S * (size_t)P.ev_idx_stride * sizeof(int32_t));
     P.off_ev_ent = region(S * (size_t)P.ev_ent_stride * sizeof(JtEv));
+    P.off_csrc = region(S * (size_t)P.csrc_stride * sizeof(int32_t));
+    P.off_work_count = region(std::max<size_t>(1, (size_t)P.n_listed) * sizeof(int32_t));
+    P.off_work = region(std::max<size_t>(1, (size_t)P.work_total) * sizeof(JtWork));
+    P.off_dyn = P.off_ev_idx;
+    P.dyn_bytes = off - P.off_ev_idx;
     P.icnt_stride = align_up(std::max<int64_t>(1, (int64_t)P.items.size()), kAlignFloats);
     P.off_icnt = region(S * (size_t)P.icnt_stride * sizeof(int32_t));
+    P.off_cltab = region(P.cltab.size() * sizeof(int64_t));
     P.total_bytes = off;
     P.slot_bytes = (size_t)P.coll_stride * sizeof(float) + (size_t)P.out_stride * sizeof(float) +
                    (size_t)P.sep_stride * sizeof(float) + (size_t)P.partial_stride * sizeof(float) +
                    (size_t)P.lam_stride * sizeof(double) + (size_t)P.scale_stride * sizeof(float) + sizeof(int32_t) +
                    (size_t)P.ev_idx_stride * sizeof(int32_t) + (size_t)P.ev_ent_stride * sizeof(JtEv) +
-                   (size_t)P.icnt_stride * sizeof(int32_t);
+                   (size_t)P.icnt_stride * sizeof(int32_t) + (size_t)P.csrc_stride * sizeof(int32_t);
     std::string why;
     if (!verify_plan(P, why)) return fail(err, JT_E_ARG, why);
     return JT_OK;
+}
+
+void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_vars, int32_t n_active, Dynamic &D) {
+    const int32_t nc = P.n_cliques, S = P.n_slots, N = P.n_slots;   // N: the evidence-free slot
+    D.csrc.assign((size_t)P.n_regions * P.csrc_stride, 0);
+    for (int32_t r = 0; r < P.n_regions; ++r)
+        for (int32_t c = 0; c < nc; ++c) D.csrc[(size_t)r * P.csrc_stride + c] = r;
+    D.work.assign((size_t)std::max<int64_t>(1, P.work_total), JtWork{0, 0});
+    D.count.assign((size_t)std::max<int32_t>(1, P.n_listed), 0);
+    D.grid.assign((size_t)std::max<int32_t>(1, P.n_listed), 1);
+    D.shared = 0;
+    D.collect_pairs = 0;
+    // dirty[s][c]: the subtree of c (schedule orientation) holds the home
+    // clique of one of slot s's observed variables; the root always is
+    std::vector<std::vector<char>> dirty((size_t)n_active, std::vector<char>(nc, 0));
+    for (int32_t s = 0; s < n_active; ++s) {
+        std::vector<char> &d = dirty[s];
+        d[P.root] = 1;
+        if (s < (int32_t)ev_vars.size())
+            for (int32_t v : ev_vars[s]) {
+                for (int32_t c = P.home[v]; c >= 0 && !d[c]; c = P.iparent[c]) d[c] = 1;
+            }
+    }
+    // share when the evidence-free slot plus the dirty passes stream fewer
+    // entries than every active slot's whole collect sweep
+    int64_t full = 0, dirty_sum = 0;
+    for (int32_t c = 0; c < nc; ++c) full += P.cl[c].size;
+    for (int32_t s = 0; s < n_active; ++s)
+        for (int32_t c = 0; c < nc; ++c)
+            if (dirty[s][c]) dirty_sum += P.cl[c].size;
+    const bool share = P.share && full + dirty_sum < (int64_t)n_active * full;
+    D.shared = share ? 1 : 0;
+    if (share)
+        for (int32_t s = 0; s < n_active; ++s)
+            for (int32_t c = 0; c < nc; ++c)
+                if (!dirty[s][c]) D.csrc[(size_t)s * P.csrc_stride + c] = N;
+    auto runs = [&](int32_t s, int32_t c) { return share ? (s == N || dirty[s][c]) : s < n_active; };
+    int64_t bytes = 0;
+    for (const Launch &l : P.fused) {
+        if (l.count == 0) continue;
+        // slots that execute each task of the launch
+        if (l.listed) {
+            int32_t k = 0;
+            for (int32_t t = 0; t < l.count; ++t) {
+                const int32_t c = P.items[P.tasks[l.begin + t].item].clique;
+                if (share) D.work[l.work_off + k++] = JtWork{t, N};
+                for (int32_t s = 0; s < n_active; ++s)
+                    if (runs(s, c)) D.work[l.work_off + k++] = JtWork{t, s};
+            }
+            D.count[l.work_idx] = k;
+            int64_t g = 1;
+            while (g < k) g *= 2;
+            D.grid[l.work_idx] = (int32_t)std::min<int64_t>(g, l.work_cap);
+        }
+        // FP32 table bytes: shared tables (initial tables, evidence-free
+        // absorbed tables) once per launch, slot tables per slot
+        int32_t last = -1;
+        for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
+            const int32_t i = P.tasks[t].item;
+            if (i == last) continue;
+            last = i;
+            const JtItem &it = P.items[i];
+            const int32_t c = it.clique;
+            const int64_t tb = 4 * P.cl[c].size;
+            if (l.collect) {
+                int64_t n = 0;
+                for (int32_t s = 0; s < n_active; ++s) n += runs(s, c) ? 1 : 0;
+                if (share) n += 1;
+                D.collect_pairs += n;
+                if (n > 0) bytes += tb;                          // initial table
+                if (it.dst_kind != JT_DST_NONE) bytes += tb * n;  // absorbed tables
+            } else {
+                if (it.src_kind == JT_SRC_INIT) {
+                    bytes += tb;
+                } else {
+                    int64_t own = 0;
+                    bool any_shared = false;
+                    for (int32_t s = 0; s < n_active; ++s) {
+                        if (D.csrc[(size_t)s * P.csrc_stride + c] == s) ++own;
+                        else any_shared = true;
+                    }
+                    bytes += tb * (own + (any_shared ? 1 : 0));
+                }
+                if (it.dst_kind != JT_DST_NONE) bytes += tb * n_active;
+            }
+        }
+    }
+    D.bytes = bytes;
+    (void)S;
 }
 
 void evidence_tables(const Plan &P, const std::vector<int32_t> &vars, const std::vector<int32_t> &states,

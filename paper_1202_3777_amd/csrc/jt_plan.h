@@ -51,6 +51,13 @@ struct Launch {
     int32_t lane = -1;      // stream: -1 the bound stream, else the lane of a root subtree
     int32_t join_before = 0;  // the bound stream first waits for every lane
     int32_t fork_after = 0;   // every lane then waits for the bound stream
+    // Listed launch (batched collect): the blocks walk a list of (task, slot)
+    // entries written per propagation, instead of every task of every slot.
+    int32_t listed = 0;
+    int64_t work_off = 0;   // first entry in the work region
+    int32_t work_cap = 0;   // entries the list can hold: count * (slots + 1)
+    int32_t work_idx = 0;   // its counter in the work-count array
+    int32_t collect = 0;    // 1: a collect-sweep launch of the fused schedule
 };
 
 struct Plan {
@@ -83,12 +90,21 @@ struct Plan {
     std::vector<JtTask> tasks;
     std::vector<JtBlock> blocks;     // device records of the tasks (same order)
     std::vector<JtMsg> msgs;
-    std::vector<int32_t> child_edges;
+    std::vector<int32_t> child_edges;   // pairs (edge id, schedule child clique)
     std::vector<Launch> fused;       // launch list of one fused propagation (finalize inside the passes)
     std::vector<Launch> plain;       // launch list of one one-at-a-time propagation
     int32_t plain_reset_task_begin = 0, plain_reset_task_count = 0;
 
+    // Batched trees (n_slots >= 2) keep one extra, evidence-free slot (index
+    // n_slots) whose collect messages every slot without evidence below an
+    // edge reads instead of computing its own; the collect launches are then
+    // listed launches.
+    int32_t share = 0;
+    int32_t n_regions = 1;           // slot regions: n_slots + share
+    int32_t n_listed = 0;            // listed launches (work counters)
+    int64_t work_total = 0;          // entries of all listed launches
     // per-slot region sizes (elements)
+    int64_t csrc_stride = 0;
     int64_t init_floats = 0, coll_stride = 0, out_stride = 0, sep_stride = 0,
             partial_stride = 0, lam_stride = 0, scale_stride = 0, ev_idx_stride = 0,
             ev_ent_stride = 0, icnt_stride = 0;
@@ -96,7 +112,12 @@ struct Plan {
     size_t off_meta = 0, off_views = 0, off_gathers = 0, off_items = 0, off_tasks = 0, off_blocks = 0,
            off_msgs = 0, off_child = 0, off_init = 0, off_coll = 0, off_out = 0, off_sep = 0,
            off_partial = 0, off_lam = 0, off_scale = 0, off_flag = 0, off_ev_idx = 0,
-           off_ev_ent = 0, off_icnt = 0, total_bytes = 0;
+           off_ev_ent = 0, off_icnt = 0, off_csrc = 0, off_work = 0, off_work_count = 0, off_cltab = 0,
+           total_bytes = 0;
+    // the part of the workspace rewritten when evidence or the active slot
+    // count change (evidence tables, collect sources, work lists): one range
+    size_t off_dyn = 0, dyn_bytes = 0;
+    std::vector<int64_t> cltab;      // per clique: posterior offset, size, packed offset
     size_t slot_bytes = 0;           // workspace bytes that scale with the slot count (per slot)
 
     // statistics
@@ -106,6 +127,25 @@ struct Plan {
 
 // Build the plan; returns JT_OK or an error code with `err` filled in.
 jt_status compile_plan(const jt_tree_desc *desc, Plan &plan, std::string &err);
+
+// Per-propagation schedule of a batched tree: which (clique, slot) pairs the
+// collect sweep computes and where every slot reads collect data from.
+struct Dynamic {
+    std::vector<int32_t> csrc;          // [n_regions][csrc_stride]
+    std::vector<JtWork> work;           // [work_total]
+    std::vector<int32_t> count;         // [n_listed]
+    std::vector<int32_t> grid;          // [n_listed] blocks launched: the count rounded up to a power of
+                                        // two (at most the list's capacity), so few graphs cover many counts
+    int64_t bytes = 0;                  // FP32 table bytes of the fused propagation it describes
+    int32_t shared = 0;                 // 1: the evidence-free slot is computed and read
+    int64_t collect_pairs = 0;          // (clique, slot) collect passes, evidence-free slot included
+};
+
+// Build the dynamic schedule for slots [0, n_active) with the given
+// evidence (one variable list per slot).  Sharing is used when it moves
+// fewer bytes than computing every slot's collect sweep.
+void build_dynamic(const Plan &plan, const std::vector<std::vector<int32_t>> &ev_vars, int32_t n_active,
+                   Dynamic &dyn);
 
 // Evidence of one slot as device digit conditions (host side).
 // idx gets n_cliques + 1 offsets into ent; ent gets the conditions.

@@ -50,9 +50,12 @@ JT_Q_ROOT = 15
 JT_Q_N_LANES = 16
 JT_Q_CLIQUE_LANE = 17
 JT_Q_FUSED_LAUNCH_LANE = 18
+JT_Q_BYTES_LAST = 19
+JT_Q_LAST_SHARED = 20
+JT_Q_LAST_COLLECT_PASSES = 21
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
-            "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
+            "jt_marginals_all", "jt_read_out", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
             "jt_free", "jt_last_error"]
 
 
@@ -103,8 +106,10 @@ def load():
     lib.jt_get_mu_lists.argtypes = [V, I32, I32, P32]
     lib.jt_query.argtypes = [V, I32, I64, P64]
     lib.jt_profile.argtypes = [V, I32, PD, PD, P32, P32]
+    lib.jt_read_out.argtypes = [V, I32, I32, V, V]
     for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
-              "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile"):
+              "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
+              "jt_read_out"):
         getattr(lib, f).restype = I32
     lib.jt_free.argtypes = [V]
     lib.jt_free.restype = None
@@ -182,6 +187,11 @@ def jt_marginals_all(h, slot: int, out_ptr: Optional[int]) -> float:
     _check(load().jt_marginals_all(h, int(slot), ctypes.c_void_p(out_ptr or 0), ctypes.byref(lz)),
            "jt_marginals_all")
     return lz.value
+
+
+def jt_read_out(h, slot0: int, n: int, posteriors_ptr: int, log_z_ptr: int):
+    _check(load().jt_read_out(h, int(slot0), int(n), ctypes.c_void_p(posteriors_ptr), ctypes.c_void_p(log_z_ptr)),
+           "jt_read_out")
 
 
 def jt_query(h, what: int, arg: int = 0) -> int:
@@ -275,7 +285,11 @@ class JunctionTree(JunctionTreePlan):
         # a stream of its own: the legacy default stream cannot be captured
         # into a graph (default priority, see the stream rules of the box)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
-        self.workspace = torch.empty(self.device_bytes, dtype=torch.uint8, device=self.device)
+        # allocated on the tree's stream, so that the caching allocator only
+        # hands the memory out again after the work queued there (jt_free
+        # also waits for that stream before the handle goes)
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(self.device_bytes, dtype=torch.uint8, device=self.device)
         pot = np.ascontiguousarray(potentials, dtype=np.float32)
         if pot.shape[0] != int(self.table_off[-1]):
             raise ValueError("potentials do not match the table sizes")

@@ -2,25 +2,31 @@
 
 Every tree is compiled once and stays on the device with its index maps and
 initial tables (Sec. 3.2: the mappings are built when the tree is
-established).  Each tree owns a HIP stream and a fixed number of evidence
-slots.  Queries arrive over time; the loop
+established).  Each tree has a few "lanes": a handle with its own workspace,
+stream and a fixed number of evidence slots, so that a tree can run several
+batches at once.  Queries arrive over time; the loop
 
-  1. retires finished batches (a device event per batch) and frees their
-     slots and memory,
-  2. admits waiting queries in arrival order while their HBM footprint (one
-     evidence slot of their tree) fits the budget -- queries that arrive while
-     others run are admitted as slots and memory free up,
-  3. launches, for every tree that is idle and has admitted queries, one
-     propagation over those queries packed into slots 0..k-1.
+  1. retires finished batches (a device event per batch, recorded after the
+     batch's posteriors have been read out into per-query device buffers)
+     and hands each result to ``on_done``;
+  2. admits waiting queries in arrival order while the device memory their
+     results need (one packed posterior buffer each, allocated at
+     admission and held until the result is handed over) fits the budget
+     beside the resident trees; a query whose tree already has a full queue
+     is skipped for now, so queries for other trees do not wait behind it;
+  3. launches, for every tree with admitted queries and an idle lane, one
+     propagation over up to ``capacity`` of them, packed into slots 0..k-1.
 
-Batches of different trees run concurrently on their own streams, so work
-of queries that arrived at different times overlaps on the device.  A
-query's result does not depend on the batch it lands in: every slot's
-summation order is fixed by its tree alone.
+Batches of different trees, and of the same tree on different lanes, run
+concurrently on their own streams, so work of queries that arrived at
+different times overlaps on the device.  A query's result does not depend
+on the batch it lands in: every slot's summation order is fixed by its tree
+alone, and evidence-free messages shared inside a batch are bit-identical to
+computed ones.
 
-Latency is measured from the arrival time to the device completion time of
-the query's batch (device events mapped onto the host clock), so it does
-not include the loop's polling delay.
+Latency is measured from the arrival time to the device completion of the
+query's read-out (device events mapped onto the host clock), so it does not
+include the loop's polling delay.
 """
 from __future__ import annotations
 
@@ -42,10 +48,12 @@ class Query:
     arrival: float                      # seconds on the loop clock
     admitted: Optional[float] = None
     launched: Optional[float] = None
-    done: Optional[float] = None        # device completion, loop clock
+    done: Optional[float] = None        # device completion of the read-out, loop clock
     slot: Optional[int] = None
+    lane: Optional[int] = None
     batch: Optional[int] = None
     status: str = "pending"             # pending, admitted, running, done, cancelled, rejected
+    result: Optional[object] = None     # executor-specific: the query's read-out buffers
     log_z: Optional[float] = None
 
     @property
@@ -57,40 +65,85 @@ class AdmissionError(RuntimeError):
     pass
 
 
-class TreeExecutor:
-    """One resident tree on the GPU: a JunctionTree with its own stream."""
+class _Lane:
+    def __init__(self, torch, jt, inst, capacity, device):
+        self.stream = torch.cuda.Stream(torch.device(device))
+        self.tree = jt.JunctionTree(inst.card, inst.clique_off, inst.clique_vars, inst.parent, inst.potentials,
+                                    n_slots=capacity, device=device, stream=self.stream)
 
-    def __init__(self, inst, capacity: int, mode: str = "graph", device: str = "cuda:0"):
+
+class TreeExecutor:
+    """One resident tree on the GPU: `lanes` handles, each with its own
+    stream, workspace and `capacity` evidence slots."""
+
+    def __init__(self, inst, capacity: int, mode: str = "graph", device: str = "cuda:0", lanes: int = 1):
         import torch
         from . import jt
         self.torch = torch
         self.jt = jt
         self.mode = mode
-        self.stream = torch.cuda.Stream(torch.device(device))
-        self.tree = jt.JunctionTree(inst.card, inst.clique_off, inst.clique_vars, inst.parent, inst.potentials,
-                                    n_slots=capacity, device=device, stream=self.stream)
+        self.device = device
         self.capacity = capacity
-        self.slot_bytes = self.tree.query(jt.JT_Q_SLOT_BYTES)
-        self.shared_bytes = self.tree.query(jt.JT_Q_SHARED_BYTES)
-        self._event = None
+        self.n_lanes = lanes
+        self.lanes = [_Lane(torch, jt, inst, capacity, device) for _ in range(lanes)]
+        t0 = self.lanes[0].tree
+        self.total_entries = int(t0.table_off[-1])
+        self.table_off = t0.table_off
+        self.n_cliques = t0.n_cliques
+        # resident: every lane's whole workspace; per query: its read-out
+        self.shared_bytes = sum(int(l.tree.device_bytes) for l in self.lanes)
+        self.query_bytes = 4 * self.total_entries + 8
 
-    def launch(self, queries: Sequence[Query]):
+    def warm(self):
+        """Capture the graphs of every batch size on every lane."""
+        for l in self.lanes:
+            for k in range(1, self.capacity + 1):
+                l.tree.propagate(self.mode, n_active=k)
+
+    def alloc_result(self, q: Query, lane: Optional[int] = None):
+        """The query's read-out buffers (posteriors, log Z) on the device."""
+        torch = self.torch
+        post = torch.empty(self.total_entries, dtype=torch.float32, device=self.device)
+        lz = torch.empty(1, dtype=torch.float64, device=self.device)
+        return post, lz
+
+    def launch(self, queries: Sequence[Query], lane: int):
+        """Propagate `queries` in slots 0..k-1 of `lane`, read each result out
+        into its own buffers, and return an event recorded after that."""
+        L = self.lanes[lane]
+        torch = self.torch
         for k, q in enumerate(queries):
-            self.tree.set_evidence(k, q.ev_vars, q.ev_states)
-        self.tree.propagate(self.mode, n_active=len(queries))
-        ev = self.torch.cuda.Event(enable_timing=True)
-        ev.record(self.stream)
-        self._event = ev
-        return ev
+            L.tree.set_evidence(k, q.ev_vars, q.ev_states)
+        L.tree.propagate(self.mode, n_active=len(queries))
+        bytes_moved = L.tree.query(self.jt.JT_Q_BYTES_LAST)
+        for k, q in enumerate(queries):
+            post, lz = q.result
+            # the buffers were allocated on the loop's stream: the lane's
+            # stream waits for that before writing them, and the caching
+            # allocator is told they are used on the lane's stream
+            L.stream.wait_stream(torch.cuda.current_stream(torch.device(self.device)))
+            post.record_stream(L.stream)
+            lz.record_stream(L.stream)
+            self.jt.jt_read_out(L.tree.handle, k, 1, post.data_ptr(), lz.data_ptr())
+            bytes_moved += 2 * 4 * self.total_entries
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(L.stream)
+        return ev, bytes_moved
 
     def done(self, ev) -> bool:
         return ev.query()
 
-    def log_z(self, slot: int) -> float:
-        return self.jt.jt_marginal(self.tree.handle, slot, 0, None)
+    def fetch(self, q: Query):
+        """The query's posteriors (packed, clique order) and log Z on the host;
+        raises the library's zero-evidence error when P(e) = 0."""
+        post, lz = q.result
+        lzh = float(lz.cpu().numpy()[0])
+        if math.isinf(lzh) and lzh < 0:
+            raise self.jt.JTError(self.jt.JT_E_ZERO_EVIDENCE, "fetch", "evidence has probability zero")
+        return post.cpu().numpy(), lzh
 
-    def marginals(self, slot: int):
-        return self.tree.marginals_all(slot)
+    def marginals(self, slot: int, lane: int = 0):
+        return self.lanes[lane].tree.marginals_all(slot)
 
 
 class Clock:
@@ -120,7 +173,7 @@ class Server:
     def __init__(self, executors: List, budget_bytes: int, clock: Optional[Clock] = None,
                  on_done: Optional[Callable] = None):
         self.ex = executors
-        self.on_done = on_done    # called as on_done(query, executor) before the slot is reused
+        self.on_done = on_done    # on_done(query, executor): called once the query's result is complete
         self.clock = clock or Clock()
         self.shared = sum(e.shared_bytes for e in executors)
         if self.shared > budget_bytes:
@@ -129,18 +182,27 @@ class Server:
         self.in_use = self.shared
         self.pending: Deque[Query] = collections.deque()
         self.waiting: List[Deque[Query]] = [collections.deque() for _ in executors]
-        self.running: List[Optional[tuple]] = [None] * len(executors)
+        self.running: List[Dict[int, tuple]] = [dict() for _ in executors]   # lane -> (event, batch)
         self.finished: List[Query] = []
         self.n_batches = 0
         self.batch_sizes: List[int] = []
+        self.table_bytes = 0      # FP32 table bytes the launched batches move (executor-reported)
+
+    @staticmethod
+    def _qbytes(e) -> int:
+        return int(getattr(e, "query_bytes", getattr(e, "slot_bytes", 0)))
+
+    @staticmethod
+    def _lanes(e) -> int:
+        return int(getattr(e, "n_lanes", 1))
 
     # -- admission ------------------------------------------------------
     def submit(self, q: Query):
         e = self.ex[q.tree]
-        if self.shared + e.slot_bytes > self.budget:
+        if self.shared + self._qbytes(e) > self.budget:
             q.status = "rejected"
             self.finished.append(q)
-            raise AdmissionError(f"query {q.qid}: one slot of tree {q.tree} does not fit the budget")
+            raise AdmissionError(f"query {q.qid}: its result does not fit the budget beside the resident trees")
         self.pending.append(q)
 
     def cancel(self, q: Query) -> bool:
@@ -149,59 +211,76 @@ class Server:
             self.pending.remove(q)
         elif q.status == "admitted":
             self.waiting[q.tree].remove(q)
-            self.in_use -= self.ex[q.tree].slot_bytes
+            self._release(q)
         else:
             return False
         q.status = "cancelled"
         self.finished.append(q)
         return True
 
+    def _release(self, q: Query):
+        self.in_use -= self._qbytes(self.ex[q.tree])
+        q.result = None if self.on_done is None else q.result
+
     def _admit(self, now: float):
+        # arrival order; a query whose tree's queue is full is passed over
+        # (it keeps its place), one that does not fit the memory budget stops
+        # admission so that later, smaller queries cannot starve it
+        skipped: List[Query] = []
         while self.pending:
-            q = self.pending[0]
+            q = self.pending.popleft()
             e = self.ex[q.tree]
             w = self.waiting[q.tree]
-            if self.in_use + e.slot_bytes > self.budget or len(w) >= e.capacity:
-                break                        # arrival order: the head waits for room
-            self.pending.popleft()
-            self.in_use += e.slot_bytes
+            if len(w) >= e.capacity * self._lanes(e):
+                skipped.append(q)
+                continue
+            if self.in_use + self._qbytes(e) > self.budget:
+                self.pending.appendleft(q)
+                break
+            self.in_use += self._qbytes(e)
+            alloc = getattr(e, "alloc_result", None)
+            q.result = alloc(q) if alloc is not None else None
             q.status = "admitted"
             q.admitted = now
             w.append(q)
+        for q in reversed(skipped):
+            self.pending.appendleft(q)
 
     # -- batches ----------------------------------------------------------
     def _retire(self):
-        for t, r in enumerate(self.running):
-            if r is None:
-                continue
-            ev, batch = r
-            if not self.ex[t].done(ev):
-                continue
-            tdone = self.clock.event_time(ev)
-            for q in batch:
-                q.done = tdone
-                q.status = "done"
-                if self.on_done is not None:
-                    self.on_done(q, self.ex[t])
-                self.finished.append(q)
-                self.in_use -= self.ex[t].slot_bytes
-            self.running[t] = None
+        for t, runs in enumerate(self.running):
+            for lane in list(runs):
+                ev, batch = runs[lane]
+                if not self.ex[t].done(ev):
+                    continue
+                tdone = self.clock.event_time(ev)
+                for q in batch:
+                    q.done = tdone
+                    q.status = "done"
+                    if self.on_done is not None:
+                        self.on_done(q, self.ex[t])
+                    self.finished.append(q)
+                    self._release(q)
+                del runs[lane]
 
     def _launch(self, now: float):
         for t, w in enumerate(self.waiting):
-            if self.running[t] is not None or not w:
-                continue
             e = self.ex[t]
-            batch = [w.popleft() for _ in range(min(len(w), e.capacity))]
-            for k, q in enumerate(batch):
-                q.slot = k
-                q.batch = self.n_batches
-                q.status = "running"
-                q.launched = now
-            ev = e.launch(batch)
-            self.running[t] = (ev, batch)
-            self.n_batches += 1
-            self.batch_sizes.append(len(batch))
+            while w and len(self.running[t]) < self._lanes(e):
+                lane = next(k for k in range(self._lanes(e)) if k not in self.running[t])
+                batch = [w.popleft() for _ in range(min(len(w), e.capacity))]
+                for k, q in enumerate(batch):
+                    q.slot = k
+                    q.lane = lane
+                    q.batch = self.n_batches
+                    q.status = "running"
+                    q.launched = now
+                r = e.launch(batch, lane)
+                ev, moved = r if isinstance(r, tuple) else (r, 0)
+                self.table_bytes += int(moved)
+                self.running[t][lane] = (ev, batch)
+                self.n_batches += 1
+                self.batch_sizes.append(len(batch))
 
     def step(self):
         now = self.clock.now()
@@ -210,7 +289,7 @@ class Server:
         self._launch(now)
 
     def busy(self) -> bool:
-        return bool(self.pending) or any(self.waiting) or any(r is not None for r in self.running)
+        return bool(self.pending) or any(self.waiting) or any(self.running)
 
     def run(self, queries: Sequence[Query], idle_sleep: float = 20e-6, max_seconds: float = 120.0):
         """Feed queries at their arrival times and serve until all finish."""

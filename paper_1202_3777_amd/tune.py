@@ -11,7 +11,12 @@ rounding order and stay within the stated tolerance.
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 # Candidates around the built-in defaults (group 8K..32K entries, 1280 blocks
 # per launch): one knob moved at a time, plus two joint moves.  (Lanes are
@@ -75,3 +80,41 @@ def autotune(inst, n_slots: Optional[int] = None, candidates: Optional[Sequence[
     """Pick the fastest shape choice for `inst` on the GPU."""
     return choose(candidates if candidates is not None else DEFAULT_CANDIDATES,
                   gpu_timer(inst, n_slots=n_slots, **timer_kw))
+
+
+def shape_key(inst, n_slots: Optional[int] = None, device_name: str = "") -> str:
+    """Shape class of a tree for the tuning cache: what the shape choices
+    depend on -- the tree's topology, every table and separator size, the
+    table layouts (tiles), the slot count and the GPU -- and nothing of the
+    potentials or the evidence."""
+    h = hashlib.sha256()
+    for a in (inst.card, inst.clique_off, inst.clique_vars, inst.parent):
+        h.update(a.tobytes())
+    h.update(str(int(n_slots if n_slots is not None else max(1, inst.n_slots))).encode())
+    h.update(device_name.encode())
+    return h.hexdigest()[:32]
+
+
+def cache_lookup(key: str, path: str = CACHE_PATH) -> Optional[Dict[str, int]]:
+    if not os.path.exists(path):
+        return None
+    try:
+        entry = json.load(open(path)).get(key)
+    except (OSError, ValueError):
+        return None
+    return None if entry is None else dict(entry["tuning"])
+
+
+def cache_store(key: str, tuning: Dict[str, int], table, note: str = "", path: str = CACHE_PATH) -> None:
+    data = {}
+    if os.path.exists(path):
+        try:
+            data = json.load(open(path))
+        except ValueError:
+            data = {}
+    data[key] = {"tuning": dict(tuning), "note": note,
+                 "candidates_ms": [[c, round(ms, 4)] for c, ms in table]}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)

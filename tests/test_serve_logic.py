@@ -25,7 +25,7 @@ class FakeExecutor:
         self.never = never
         self.launches = []
 
-    def launch(self, queries):
+    def launch(self, queries, lane=0):
         t = self.clock.now()
         self.launches.append((t, [q.qid for q in queries]))
         return FakeEvent(float("inf") if self.never else t + self.dt)
@@ -120,3 +120,39 @@ def test_loop_time_limit():
     srv = Server(ex, budget_bytes=10 ** 9, clock=clock)
     with pytest.raises(TimeoutError):
         srv.run(_queries(1, 2, None), max_seconds=0.2)
+
+
+def test_full_tree_queue_does_not_block_other_trees():
+    # tree 0 gets a burst larger than its queue; a later query for tree 1 is
+    # admitted and launched before tree 0's backlog drains
+    clock = Clock()
+    ex = [FakeExecutor(clock, capacity=2, slot_bytes=1, shared_bytes=0, seconds_per_batch=0.02) for _ in range(2)]
+    srv = Server(ex, budget_bytes=10 ** 9, clock=clock)
+    qs = [Query(qid=k, tree=0, ev_vars=np.zeros(0, np.int32), ev_states=np.zeros(0, np.int32), arrival=0.0)
+          for k in range(8)]
+    qs.append(Query(qid=8, tree=1, ev_vars=np.zeros(0, np.int32), ev_states=np.zeros(0, np.int32), arrival=0.001))
+    done = srv.run(qs, max_seconds=20)
+    assert all(q.status == "done" for q in done)
+    last0 = max(q.launched for q in qs if q.tree == 0)
+    assert qs[8].launched < last0
+
+
+def test_lanes_overlap_batches_of_one_tree():
+    clock = Clock()
+    e = FakeExecutor(clock, capacity=2, slot_bytes=1, shared_bytes=0, seconds_per_batch=0.05)
+    e.n_lanes = 2
+    srv = Server([e], budget_bytes=10 ** 9, clock=clock)
+    qs = [Query(qid=k, tree=0, ev_vars=np.zeros(0, np.int32), ev_states=np.zeros(0, np.int32), arrival=0.002 * k)
+          for k in range(4)]
+    peak = 0
+    orig = srv._launch
+
+    def spy(now):
+        nonlocal peak
+        orig(now)
+        peak = max(peak, len(srv.running[0]))
+    srv._launch = spy
+    done = srv.run(qs, max_seconds=20)
+    assert all(q.status == "done" for q in done)
+    assert peak == 2                                 # two batches of the same tree in flight
+    assert {q.lane for q in qs} == {0, 1}
