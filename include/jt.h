@@ -272,6 +272,33 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_ms, int32_t *n_pass,
                      int32_t *n_finalize);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): one propagation of every slot of a compiled tree in a static device
+ * scratch array owned by the library (128 MiB per GPU, held until the
+ * process ends) instead of a caller workspace; no jt_bind is
+ * needed and the handle's own binding, if any, is left untouched.  The
+ * library calls no device allocator here.
+ *   init_potentials  device pointer, FP32 tables concatenated in clique order;
+ *   posteriors       device pointer, n_slots * sum |phi_X| floats: every
+ *                    slot's normalized clique posteriors, clique order, slot
+ *                    after slot (undefined for a slot whose evidence has
+ *                    probability zero);
+ *   log_z            device pointer, n_slots doubles: log Z_e per slot, -inf
+ *                    when the evidence has probability zero;
+ *   mode             JT_MODE_FUSED or JT_MODE_PLAIN;
+ *   hip_stream       stream the work is enqueued on (asynchronous).
+ * The evidence is the handle's (jt_set_evidence).  Every call on one GPU
+ * uses that GPU's one scratch array, which keeps the last call's contents:
+ * calls that overlap on one GPU (different streams, or a second call before
+ * the first has finished reading its inputs) race, and the handle must stay
+ * alive, with its evidence unchanged, until the stream has run the call.
+ * Results are bit-identical to jt_bind + jt_propagate in the same mode.
+ * Errors: JT_E_ARG, JT_E_NO_MEM (the tree's workspace exceeds the scratch;
+ * nothing is launched), JT_E_HIP. */
+jt_status jt_propagate_scratch(jt_tree t, const float *init_potentials, float *posteriors, double *log_z,
+                               int32_t mode, void *hip_stream);
+
 /* Release the handle and its host-side objects (captured graphs included),
  * after the work queued on its bound stream has finished.  Device memory
  * stays the caller's.  NULL is ignored. */

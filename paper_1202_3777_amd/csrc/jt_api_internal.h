@@ -44,6 +44,10 @@ struct jt_tree_s {
     int64_t last_bytes = 0;
     int last_shared = 0;
     int64_t last_collect_pairs = 0;
+    // host copies the scratch entry point uploads from (kept until its next call)
+    std::vector<int32_t> sx_ev_idx;
+    std::vector<JtEv> sx_ev_ent;
+    jt::Dynamic sx_dyn;
     // captured graphs of the level launches, keyed by the number of active
     // slots followed by the grids of the listed launches
     std::map<std::vector<int32_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;

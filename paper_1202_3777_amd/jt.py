@@ -56,7 +56,7 @@ JT_Q_LAST_COLLECT_PASSES = 21
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_read_out", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
-            "jt_free", "jt_last_error"]
+            "jt_propagate_scratch", "jt_free", "jt_last_error"]
 
 
 class JTError(RuntimeError):
@@ -106,10 +106,11 @@ def load():
     lib.jt_get_mu_lists.argtypes = [V, I32, I32, P32]
     lib.jt_query.argtypes = [V, I32, I64, P64]
     lib.jt_profile.argtypes = [V, I32, PD, PD, P32, P32]
+    lib.jt_propagate_scratch.argtypes = [V, V, V, V, I32, V]
     lib.jt_read_out.argtypes = [V, I32, I32, V, V]
     for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
               "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
-              "jt_read_out"):
+              "jt_propagate_scratch", "jt_read_out"):
         getattr(lib, f).restype = I32
     lib.jt_free.argtypes = [V]
     lib.jt_free.restype = None
@@ -219,6 +220,14 @@ def jt_profile(h, mode: int = JT_MODE_FUSED):
     _check(load().jt_profile(h, int(mode), ctypes.byref(pm), ctypes.byref(fm), ctypes.byref(npass),
                              ctypes.byref(nfin)), "jt_profile")
     return pm.value, fm.value, npass.value, nfin.value
+
+
+def jt_propagate_scratch(h, init_ptr: int, posteriors_ptr: int, log_z_ptr: int, mode: int, stream_ptr: int):
+    """One propagation of every slot in the library's static device scratch
+    (no device allocation); all pointers are device pointers."""
+    _check(load().jt_propagate_scratch(h, ctypes.c_void_p(init_ptr), ctypes.c_void_p(posteriors_ptr),
+                                       ctypes.c_void_p(log_z_ptr), int(mode), ctypes.c_void_p(stream_ptr)),
+           "jt_propagate_scratch")
 
 
 def jt_free(h):
