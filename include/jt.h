@@ -72,13 +72,17 @@ typedef int32_t jt_status;
  *                  message, tables updated in place;
  *   JT_MODE_DATAFLOW  reserved for a persistent schedule that overlaps tree
  *                  levels; disabled: jt_propagate and jt_profile return
- *                  JT_E_ARG for it.
- * In every schedule a message is finalized (new separator table, rescale,
+ *                  JT_E_ARG for it;
+ *   JT_MODE_PAPER, JT_MODE_PAPER_GRAPH  the paper's own kernel design (see
+ *                  jt_paper_bind).
+ * In the first three a message is finalized (new separator table, rescale,
  * ratio, log-scales) inside the pass launch that produces it. */
 #define JT_MODE_FUSED 0
 #define JT_MODE_GRAPH 1
 #define JT_MODE_PLAIN 2
 #define JT_MODE_DATAFLOW 3
+#define JT_MODE_PAPER 4
+#define JT_MODE_PAPER_GRAPH 5
 
 typedef struct jt_tree_s *jt_tree;
 
@@ -178,6 +182,32 @@ jt_status jt_marginal(jt_tree t, int32_t slot, int32_t clique, float *out, doubl
  * (sum of |phi_X| floats, host or device pointer).  Same errors as
  * jt_marginal. */
 jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z);
+
+/* The paper's own kernel design, kept as an ablation of the tiled engine
+ * (Sec. 3.2 Algorithm 1, Sec. 4.5 Fig. 8): jt_propagate with
+ * JT_MODE_PAPER (or JT_MODE_PAPER_GRAPH, the same launches replayed from a
+ * captured graph) runs one message at a time in the order of Algorithms 2-3
+ * on the caller's root, children ascending, each evidence set after the
+ * other; a message is three launches with one thread per separator entry j:
+ * marginalize through the explicit mapping list mu(j), normalize (sigma,
+ * log-scales, new/old with 0/0 := 0) and scatter-multiply through mu(j) of
+ * the receiving table.  The mapping lists live in a second caller workspace:
+ *   jt_paper_bytes    its size;
+ *   jt_paper_bind     build the lists on the host (after jt_bind) in
+ *                     `layout`: JT_LAYOUT_NAIVE (list j contiguous) or
+ *                     JT_LAYOUT_INTERLEAVED (entry n of all lists contiguous,
+ *                     Fig. 8's improved layout), upload them and set the
+ *                     threads per block (1..1024) of the per-entry kernels;
+ *                     synchronizes the bound stream.  May be called again
+ *                     to switch layout or block size.
+ * Results equal the other schedules' within the stated tolerance, and are
+ * bit-identical between the two layouts and across block sizes.
+ * Errors: JT_E_ARG, JT_E_STATE (jt_bind missing), JT_E_NO_MEM, JT_E_HIP;
+ * jt_propagate with a paper mode before jt_paper_bind returns JT_E_STATE. */
+#define JT_LAYOUT_NAIVE 0
+#define JT_LAYOUT_INTERLEAVED 1
+jt_status jt_paper_bytes(jt_tree t, size_t *bytes);
+jt_status jt_paper_bind(jt_tree t, void *workspace, size_t bytes, int32_t layout, int32_t threads_per_block);
 
 /* Asynchronous read-out on the bound stream: the posteriors of slots
  * [slot0, slot0 + n) packed in clique order, slot after slot

@@ -17,7 +17,12 @@
 
 hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slots, int lds_floats, int flags,
                           int64_t work_off, int work_idx, int grid, hipStream_t s);
+hipError_t jt_launch_pass_multi(const JtDev &d, int task_begin, int lds_floats, int64_t work_off, int work_idx,
+                                int grid, hipStream_t s);
 hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s);
+hipError_t jt_launch_paper_slot(const JtDev &d, const JtPaperMsg *host_msgs, int n_msgs, const JtPaperBlk *dev_blocks,
+                                int n_blocks, const int32_t *dev_mu, int32_t layout, int32_t tpb, int32_t root,
+                                int slot, hipStream_t s);
 hipError_t jt_launch_read_out(const JtDev &d, int slot0, int n_slots, int64_t packed_total, float *dst,
                               double *log_z, hipStream_t s);
 
@@ -122,6 +127,7 @@ void fill_dev(const jt::Plan &P, char *base, JtDev &d) {
     d.csrc = reinterpret_cast<const int32_t *>(base + P.off_csrc);
     d.work = reinterpret_cast<const JtWork *>(base + P.off_work);
     d.work_count = reinterpret_cast<const int32_t *>(base + P.off_work_count);
+    d.chunks = reinterpret_cast<const JtChunk *>(base + P.off_chunks);
     d.cltab = reinterpret_cast<const int64_t *>(base + P.off_cltab);
     d.coll_stride = P.coll_stride;
     d.out_stride = P.out_stride;
@@ -200,6 +206,8 @@ jt_status prepare(jt_tree t, int n_active, bool fused) {
             jt::build_dynamic(P, t->ev_vars, n_active, t->dyn);
         } catch (const std::bad_alloc &) {
             return set_err(JT_E_NO_MEM, "host allocation failed");
+        } catch (const std::exception &x) {
+            return set_err(JT_E_ARG, std::string("schedule: ") + x.what());
         }
         t->dyn_version = t->ev_version;
         t->dyn_n_active = n_active;
@@ -211,6 +219,9 @@ jt_status prepare(jt_tree t, int n_active, bool fused) {
         if (e == hipSuccess)
             e = stage_put(t->stage, t->ws + P.off_work, t->dyn.work.data(), t->dyn.work.size() * sizeof(JtWork),
                           t->stream);
+        if (e == hipSuccess && P.chunk_total > 0)
+            e = stage_put(t->stage, t->ws + P.off_chunks, t->dyn.chunks.data(),
+                          t->dyn.chunks.size() * sizeof(JtChunk), t->stream);
     }
     hipError_t e2 = stage_end(t->stage, t->stream);
     if (e != hipSuccess) return hip_err(e, "evidence upload");
@@ -270,8 +281,11 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
                 grid = (*grids)[l.work_idx];
                 if (grid < 1 || grid > l.work_cap) return set_err(JT_E_STATE, "listed grid out of range");
             }
-            e = jt_launch_pass(d, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, l, fused, S),
-                               l.listed ? l.work_off : -1, l.work_idx, grid, s);
+            if (l.multi)
+                e = jt_launch_pass_multi(d, l.begin, l.lds_floats, l.work_off, l.work_idx, grid, s);
+            else
+                e = jt_launch_pass(d, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, l, fused, S),
+                                   l.listed ? l.work_off : -1, l.work_idx, grid, s);
         }
         if (e != hipSuccess) return hip_err(e, "kernel launch");
         if (l.fork_after && lanes) {
@@ -289,6 +303,20 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
 }  // namespace jt_detail
 
 namespace {
+
+// The paper-faithful schedule for slots [0, S): separators := 1 and
+// log-scales := 0 for all, then each slot's messages one after the other.
+jt_status enqueue_paper(jt_tree t, int S, hipStream_t stream) {
+    const jt::PaperPlan &pp = t->paper;
+    hipError_t e = jt_launch_plain_init(t->dev, S, stream);
+    for (int s = 0; s < S && e == hipSuccess; ++s)
+        e = jt_launch_paper_slot(t->dev, pp.msgs.data(), (int)pp.msgs.size(),
+                                 reinterpret_cast<const JtPaperBlk *>(t->paper_ws + pp.off_blocks),
+                                 (int)pp.blocks.size(), reinterpret_cast<const int32_t *>(t->paper_ws + pp.off_mu),
+                                 t->paper_layout, t->paper_tpb, t->plan.user_root, s, stream);
+    if (e != hipSuccess) return hip_err(e, "paper schedule launch");
+    return JT_OK;
+}
 
 void drop_lanes(jt_tree t) {
     for (hipStream_t s : t->lane_stream)
@@ -314,9 +342,13 @@ void drop_graph(jt_tree t) {
 // Capture the launches of one propagation once per number of active slots
 // (and, for a batched tree, per set of listed grid sizes), then replay the
 // graph.
-jt_status run_graph(jt_tree t, int S) {
-    std::vector<int32_t> key{S};
-    if (t->plan.share) key.insert(key.end(), t->dyn.grid.begin(), t->dyn.grid.end());
+jt_status run_graph(jt_tree t, int S, bool paper = false) {
+    std::vector<int32_t> key{paper ? -S : S};
+    if (t->plan.share && !paper) key.insert(key.end(), t->dyn.grid.begin(), t->dyn.grid.end());
+    if (paper) {
+        key.push_back(t->paper_layout);
+        key.push_back(t->paper_tpb);
+    }
     auto f = t->graphs.find(key);
     if (f == t->graphs.end()) {
         if (t->graphs.size() >= kMaxGraphs) {
@@ -327,7 +359,8 @@ jt_status run_graph(jt_tree t, int S) {
         }
         hipError_t e = hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_err(e, "begin capture");
-        jt_status rc = enqueue(t, t->dev, t->plan.fused, S, true, t->stream, &t->dyn.grid);
+        jt_status rc = paper ? enqueue_paper(t, S, t->stream)
+                             : enqueue(t, t->dev, t->plan.fused, S, true, t->stream, &t->dyn.grid);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(t->stream, &g);
         if (rc != JT_OK) {
@@ -351,7 +384,16 @@ jt_status run_graph(jt_tree t, int S) {
 // Record what the propagation just enqueued moves (FP32 table bytes).
 void note_last(jt_tree t, int mode, int n_active) {
     const jt::Plan &P = t->plan;
-    if (mode == JT_MODE_PLAIN) {
+    if (mode == JT_MODE_PAPER || mode == JT_MODE_PAPER_GRAPH) {
+        // tables: reset (init read, table written), each message reads the
+        // sender and reads and writes the receiver, read-out reads and
+        // writes every table; mapping lists are not counted
+        int64_t b = 0;
+        for (const JtPaperMsg &m : t->paper.msgs) b += 4 * (m.m_from + 2 * (int64_t)m.m_to) * m.ssize;
+        t->last_bytes = (b + 4 * 4 * P.total_entries) * n_active;
+        t->last_shared = 0;
+        t->last_collect_pairs = 0;
+    } else if (mode == JT_MODE_PLAIN) {
         t->last_bytes = P.bytes_plain;
         t->last_shared = 0;
         t->last_collect_pairs = 0;
@@ -494,13 +536,20 @@ jt_status jt_set_evidence(jt_tree t, int32_t slot, int32_t n_obs, const int32_t 
 jt_status jt_propagate_n(jt_tree t, int32_t mode, int32_t n_active) {
     if (jt_status rc = check_tree(t)) return rc;
     if (!t->bound) return set_err(JT_E_STATE, "jt_propagate before jt_bind");
-    if (mode != JT_MODE_FUSED && mode != JT_MODE_GRAPH && mode != JT_MODE_PLAIN && mode != JT_MODE_DATAFLOW)
+    if (mode != JT_MODE_FUSED && mode != JT_MODE_GRAPH && mode != JT_MODE_PLAIN && mode != JT_MODE_DATAFLOW &&
+        mode != JT_MODE_PAPER && mode != JT_MODE_PAPER_GRAPH)
         return set_err(JT_E_ARG, "unknown mode");
     if (n_active < 1 || n_active > t->plan.n_slots) return set_err(JT_E_ARG, "n_active out of range");
     if (mode == JT_MODE_DATAFLOW) return dataflow_disabled();
-    if (jt_status rc = prepare(t, n_active, mode != JT_MODE_PLAIN)) return rc;
+    const bool paper = mode == JT_MODE_PAPER || mode == JT_MODE_PAPER_GRAPH;
+    if (paper && !t->paper_ws) return set_err(JT_E_STATE, "paper schedule before jt_paper_bind");
+    if (jt_status rc = prepare(t, n_active, mode == JT_MODE_FUSED || mode == JT_MODE_GRAPH)) return rc;
     jt_status rc = JT_OK;
-    if (mode == JT_MODE_FUSED)
+    if (mode == JT_MODE_PAPER)
+        rc = enqueue_paper(t, n_active, t->stream);
+    else if (mode == JT_MODE_PAPER_GRAPH)
+        rc = run_graph(t, n_active, true);
+    else if (mode == JT_MODE_FUSED)
         rc = enqueue(t, t->dev, t->plan.fused, n_active, true, t->stream, &t->dyn.grid);
     else if (mode == JT_MODE_PLAIN)
         rc = enqueue(t, t->dev, t->plan.plain, n_active, false, t->stream, nullptr);
@@ -573,6 +622,59 @@ jt_status jt_read_out(jt_tree t, int32_t slot0, int32_t n, float *posteriors, do
     if (slot0 + n > t->last_n_active) return set_err(JT_E_STATE, "slot was not active in the last propagation");
     hipError_t e = jt_launch_read_out(t->dev, slot0, n, P.total_entries, posteriors, log_z, t->stream);
     if (e != hipSuccess) return hip_err(e, "read-out launch");
+    return JT_OK;
+}
+
+jt_status jt_paper_bytes(jt_tree t, size_t *bytes) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!bytes) return set_err(JT_E_ARG, "bytes is NULL");
+    try {
+        if (!t->paper_planned) {
+            jt::build_paper_plan(t->plan, t->paper);
+            t->paper_planned = true;
+        }
+    } catch (const std::bad_alloc &) {
+        return set_err(JT_E_NO_MEM, "host allocation failed");
+    }
+    *bytes = t->paper.bytes;
+    return JT_OK;
+}
+
+jt_status jt_paper_bind(jt_tree t, void *workspace, size_t bytes, int32_t layout, int32_t threads_per_block) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!t->bound) return set_err(JT_E_STATE, "jt_paper_bind before jt_bind");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return set_err(JT_E_ARG, "paper workspace NULL or not 256-byte aligned");
+    if (layout != JT_LAYOUT_NAIVE && layout != JT_LAYOUT_INTERLEAVED) return set_err(JT_E_ARG, "unknown layout");
+    if (threads_per_block < 1 || threads_per_block > 1024) return set_err(JT_E_ARG, "threads per block out of range");
+    size_t need = 0;
+    if (jt_status rc = jt_paper_bytes(t, &need)) return rc;
+    if (bytes < need) return set_err(JT_E_NO_MEM, "paper workspace of " + std::to_string(bytes) + " bytes, need " +
+                                                      std::to_string(need));
+    const jt::PaperPlan &pp = t->paper;
+    hipError_t e = hipStreamSynchronize(t->stream);   // nothing queued still reads the old lists
+    if (e != hipSuccess) return hip_err(e, "stream synchronize");
+    try {
+        std::vector<int32_t> mu((size_t)std::max<int64_t>(1, pp.mu_total));
+        jt::paper_mu_lists(t->plan, pp, layout, mu.data());
+        char *ws = static_cast<char *>(workspace);
+        e = hipMemcpyAsync(ws + pp.off_msgs, pp.msgs.data(), pp.msgs.size() * sizeof(JtPaperMsg),
+                           hipMemcpyHostToDevice, t->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws + pp.off_blocks, pp.blocks.data(), pp.blocks.size() * sizeof(JtPaperBlk),
+                               hipMemcpyHostToDevice, t->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws + pp.off_mu, mu.data(), (size_t)pp.mu_total * sizeof(int32_t), hipMemcpyHostToDevice,
+                               t->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(t->stream);   // `mu` is freed on return
+    } catch (const std::bad_alloc &) {
+        return set_err(JT_E_NO_MEM, "host allocation failed");
+    }
+    if (e != hipSuccess) return hip_err(e, "paper workspace upload");
+    // graphs of the paper schedule captured for another layout or block size stay valid (keyed by both)
+    t->paper_ws = static_cast<char *>(workspace);
+    t->paper_layout = layout;
+    t->paper_tpb = threads_per_block;
     return JT_OK;
 }
 
@@ -702,6 +804,9 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
                 e = jt_launch_plain_init(t->dev, S, t->stream);
             else if (l.listed && (size_t)l.work_idx >= t->dyn.grid.size())
                 e = hipErrorInvalidValue;
+            else if (l.multi)
+                e = jt_launch_pass_multi(t->dev, l.begin, l.lds_floats, l.work_off, l.work_idx,
+                                         t->dyn.grid[l.work_idx], t->stream);
             else
                 e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, l, fused, S),
                                    l.listed ? l.work_off : -1, l.work_idx, l.listed ? t->dyn.grid[l.work_idx] : 0,

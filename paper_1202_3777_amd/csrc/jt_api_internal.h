@@ -57,6 +57,12 @@ struct jt_tree_s {
     hipEvent_t fork_ev = nullptr;
     int last_mode = -1;
     int last_n_active = 0;
+    // paper-faithful schedule: its plan, its workspace (mapping lists,
+    // message and block records), layout and threads per block
+    jt::PaperPlan paper;
+    bool paper_planned = false;
+    char *paper_ws = nullptr;
+    int32_t paper_layout = 0, paper_tpb = 0;
 };
 
 namespace jt_detail {

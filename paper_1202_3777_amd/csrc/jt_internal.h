@@ -35,8 +35,12 @@
 #endif
 /* Lanes are switched off: the first GPU run with them ended in a host-side
  * segmentation fault inside a graph propagation (cause not found), so
- * max_lanes must stay 1 and every level runs on the bound stream. */
+ * max_lanes must stay 1 and every level runs on the bound stream.  (Only the
+ * sanitized host build of the planner turns them on, to check their
+ * planning.) */
+#ifndef JT_LANES_ENABLED
 #define JT_LANES_ENABLED 0
+#endif
 #ifndef JT_WAVE_GROUP_TILES
 #define JT_WAVE_GROUP_TILES 16    /* output views with at most this many tiles per kept-outer configuration use wave groups */
 #endif
@@ -152,10 +156,41 @@ typedef struct {
 #define JT_LAM_LOGZ(nc) (3 * (nc))
 
 // One entry of a listed launch: block-task `task` (relative to the launch's
-// first task) of slot `slot`.
+// first task) of slot `slot`; in a multi-slot launch `slot` indexes a
+// JtChunk instead.  task = -1: padding, the block returns at once.
 typedef struct {
     int32_t task, slot;
 } JtWork;
+
+// Up to JT_MS slots that read the same (evidence-free) source table in one
+// multi-slot distribute pass; unused entries are -1 (the used ones first).
+#define JT_MS 4
+typedef struct {
+    int32_t s[JT_MS];
+} JtChunk;
+
+// Paper-faithful schedule (the ablation of the paper's own kernel design):
+// one message at a time in Algorithm 2-3 order, one thread per separator
+// entry reading explicit mapping lists (Algorithm 1), in the naive layout
+// (list j contiguous) or the interleaved one (entry n of every list
+// contiguous, Fig. 8).
+#define JT_LAYOUT_NAIVE_ 0
+#define JT_LAYOUT_INTERLEAVED_ 1
+typedef struct {
+    int64_t mu_from, mu_to;     // int32 offsets of the two mapping-list sets in the paper workspace
+    int64_t from_off, to_off;   // float offsets of the two tables in a slot's posterior region
+    int32_t m_from, m_to;       // list lengths |phi_X| / |phi_S|
+    int32_t ssize, edge, from, to;
+    int32_t sepc_off, sepd_off; // old table and new/ratio table of the edge
+} JtPaperMsg;
+
+// A block of the paper schedule's per-entry kernels: entries [start, end) of
+// one clique's table.
+typedef struct {
+    int32_t clique, T;          // the clique and its tile (for the evidence digits)
+    int64_t start, end;
+    int64_t init_off, out_off;  // float offsets of its initial table and of its posterior in a slot
+} JtPaperBlk;
 
 // Everything a kernel needs, passed by value.
 typedef struct {
@@ -187,6 +222,7 @@ typedef struct {
     const int32_t *csrc;
     const JtWork *work;            // entries of the listed launches
     const int32_t *work_count;     // entries per listed launch
+    const JtChunk *chunks;         // slot sets of the multi-slot entries
     const int64_t *cltab;          // per clique: posterior offset, size, packed offset
     int64_t coll_stride, out_stride, sep_stride, partial_stride;
     int64_t lam_stride, scale_stride, ev_idx_stride, ev_ent_stride;

@@ -154,6 +154,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     const int ng = it.n_gather;
     const int ngr = ng < JT_NG_REG ? ng : JT_NG_REG;
     GatherReg gr[JT_NG_REG];
+    int32_t gglob[JT_NG_REG];   // float offset of each gathered table in `sep`
     int jin[JT_NG_REG][4];
     // float offset of a gathered table in `sep` (all slot regions of the
     // separator area stay below 2^31 floats): a collect message is read from
@@ -167,13 +168,15 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
         gr[g].jout_off = 0;
         gr[g].in_lds = 0;
         gr[g].off = 0;
+        gglob[g] = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) jin[g][q] = 0;
         if (g < ngr) {
             const JtGather G = gfirst[g];
             gr[g].jout_off = G.jout_off;
             gr[g].in_lds = G.lds_off >= 0;
-            gr[g].off = G.lds_off >= 0 ? G.lds_off : gather_off(G);
+            gglob[g] = gather_off(G);
+            gr[g].off = G.lds_off >= 0 ? G.lds_off : gglob[g];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (valid[q]) jin[g][q] = meta[G.jin_off + pos[q]];
@@ -303,8 +306,26 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     // LDS staging (ratio tables, the output view's class tables); every wave
     // calls it once, after its first chunk's tile loads are in flight
     auto stage = [&]() {
-        for (int gg = 0; gg < it.n_gather_lds; ++gg) {
-            const JtGather G = gg < JT_NG_REG ? gfirst[gg] : gathers[it.gather_base + gg];
+        // the first JT_NG_REG tables: per round of 256 entries, every table's
+        // load is issued before any is stored (one memory round trip, not one
+        // per table); tables beyond them one after the other
+        const int ngl = it.n_gather_lds;
+        int jmax = 0;
+#pragma unroll
+        for (int g = 0; g < JT_NG_REG; ++g)
+            if (g < ngl && g < ngr) jmax = max(jmax, (int)gfirst[g].ssize);
+        for (int j0 = 0; j0 < jmax; j0 += JT_BLOCK) {
+            const int j = j0 + threadIdx.x;
+            float r[JT_NG_REG];
+#pragma unroll
+            for (int g = 0; g < JT_NG_REG; ++g)
+                r[g] = (g < ngl && g < ngr && j < gfirst[g].ssize) ? sep[gglob[g] + j] : 0.f;
+#pragma unroll
+            for (int g = 0; g < JT_NG_REG; ++g)
+                if (g < ngl && g < ngr && j < gfirst[g].ssize) lds_ratio[gfirst[g].lds_off + j] = r[g];
+        }
+        for (int gg = JT_NG_REG; gg < ngl; ++gg) {
+            const JtGather G = gathers[it.gather_base + gg];
             const float *__restrict__ gt = sep + gather_off(G);
             for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = gt[j];
         }
@@ -452,6 +473,258 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
         __syncthreads();
         if (wave == 0)
             fold_store(L.pos, L, it.o_n_cls, it.o_m_in, part + (int64_t)sp * it.o_ssize + meta[it.o_kout_j + k], lane);
+    }
+}
+
+// Multi-slot distribute pass: up to JT_MS slots whose pass over this
+// clique reads the same source table (the evidence-free absorbed table, or
+// the initial table of a leaf without evidence in any of them).  Every tile
+// is loaded once; for each slot k it is multiplied by that slot's parent ratio
+// (staged in LDS at k * ldsz) and scale, stored as the slot's posterior and
+// summed into the slot's partial rows -- in the same order, with the same
+// groups and folds, as the single-slot pass, so each slot's bits equal those
+// of its own pass.
+template <int VEC>
+__device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task, const int32_t *ms_slot, int ns,
+                                           const JtGather &G, const int32_t *__restrict__ meta,
+                                           const float *__restrict__ src, float *__restrict__ out,
+                                           const float *__restrict__ sep, const float *__restrict__ scale_arr,
+                                           float *__restrict__ partial, const PassStrides &st,
+                                           float *__restrict__ lds_ratio, PassLds &L,
+                                           float (*__restrict__ posk)[JT_TILE_MAX], const int64_t *ms_part,
+                                           const int64_t *ms_dst, const float *ms_scl) {
+    const int lane = threadIdx.x & (JT_WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / JT_WAVE);
+    const int T = it.T;
+    int pos[4];
+    bool valid[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        pos[q] = (VEC == 4) ? 4 * lane + q : lane + JT_WAVE * q;
+        valid[q] = pos[q] < T;
+    }
+    int jin[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) jin[q] = valid[q] ? meta[G.jin_off + pos[q]] : 0;
+    // per slot (in LDS, read as broadcasts): scale ms_scl[k], posterior
+    // offset ms_dst[k], partial-row offset ms_part[k]
+    const int ldsz = (G.ssize + 3) & ~3;
+    const bool has_dst = it.dst_kind == JT_DST_OUT;
+    const bool has_out = it.out_view >= 0;
+    const int32_t rout_off = it.o_rout_tile;
+
+    auto issue = [&](TileBatch &B, int u0, int nt, int my_o) {
+#pragma unroll
+        for (int u = 0; u < JT_UNROLL; ++u) {
+            const int uu = u0 + u;
+            B.o[u] = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) B.x[u][q] = 0.f;
+            if (uu < nt) {
+                const int o = __builtin_amdgcn_readlane(my_o, uu);
+                B.o[u] = o;
+                const float *base = src + (int64_t)o * T;
+                if (VEC == 4) {
+                    if (valid[0]) {
+                        const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
+                        B.x[u][0] = v4.x;
+                        B.x[u][1] = v4.y;
+                        B.x[u][2] = v4.z;
+                        B.x[u][3] = v4.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (valid[q]) B.x[u][q] = base[pos[q]];
+                }
+            }
+        }
+    };
+    auto consume_one = [&](const TileBatch &B, int u, int uu, int my_jo, float (&acc)[JT_MS][4]) {
+        const int o = B.o[u];
+        const int jo = __builtin_amdgcn_readlane(my_jo, uu);
+#pragma unroll
+        for (int k = 0; k < JT_MS; ++k) {
+            if (k >= ns) break;
+            const float *__restrict__ rk = lds_ratio + k * ldsz + jo;
+            const float sk = ms_scl[k];
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[q] = B.x[u][q] * rk[jin[q]];
+                v[q] = v[q] * sk;
+            }
+            if (has_dst) {
+                float *b = out + ms_dst[k] + (int64_t)o * T;
+                if (VEC == 4) {
+                    if (valid[0]) st_nt4(b + pos[0], v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (valid[q]) __builtin_nontemporal_store(v[q], b + pos[q]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[k][q] += v[q];
+        }
+    };
+    auto consume = [&](const TileBatch &B, int u0, int nt, int my_jo, float (&acc)[JT_MS][4]) {
+#pragma unroll
+        for (int u = 0; u < JT_UNROLL; ++u) {
+            if (u0 + u >= nt) break;
+            consume_one(B, u, u0 + u, my_jo, acc);
+        }
+    };
+    auto stage = [&]() {
+        // every slot's ratio table: all loads of a round issued before any
+        // is stored (one memory round trip per 256 entries, not per slot)
+        for (int j0 = 0; j0 < G.ssize; j0 += JT_BLOCK) {
+            const int j = j0 + threadIdx.x;
+            float r[JT_MS];
+#pragma unroll
+            for (int k = 0; k < JT_MS; ++k)
+                r[k] = (k < ns && j < G.ssize) ? sep[(int64_t)ms_slot[k] * st.sep + G.sep_off + j] : 0.f;
+#pragma unroll
+            for (int k = 0; k < JT_MS; ++k)
+                if (k < ns && j < G.ssize) lds_ratio[k * ldsz + j] = r[k];
+        }
+        if (has_out) {
+            for (int t = threadIdx.x; t < T; t += JT_BLOCK) L.perm[t] = meta[it.o_perm + t];
+            for (int t = threadIdx.x; t < it.o_n_cls; t += JT_BLOCK) L.clsj[t] = meta[it.o_clsj + t];
+        }
+        __syncthreads();
+    };
+    TileBatch A, B;
+    float acc[JT_MS][4];
+#pragma unroll
+    for (int k = 0; k < JT_MS; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[k][q] = 0.f;
+
+    if (it.wave_groups) {
+        const int ngrp = task.g1 - task.g0;
+        const int per = (ngrp + JT_WAVES_PER_BLOCK - 1) / JT_WAVES_PER_BLOCK;
+        const int gw0 = task.g0 + min(ngrp, wave * per), gw1 = task.g0 + min(ngrp, wave * per + per);
+        const int nr = it.tpg;
+        const int n_my = (gw1 - gw0) * nr;
+        float *row = L.red[wave];
+        int cur_g = -1, cur_jk = 0;
+        auto flush = [&]() {
+#pragma unroll
+            for (int k = 0; k < JT_MS; ++k) {
+                if (k >= ns) break;
+                wave_sync();
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (valid[q]) row[pos[q]] = acc[k][q];
+                wave_sync();
+                fold_store(row, L, it.o_n_cls, it.o_m_in, partial + ms_part[k] + cur_jk, lane);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[k][q] = 0.f;
+            }
+        };
+        auto consume_w = [&](const TileBatch &Bt, int u0, int nt, int my_g, int my_jk, int my_jo) {
+#pragma unroll
+            for (int u = 0; u < JT_UNROLL; ++u) {
+                const int uu = u0 + u;
+                if (uu >= nt) break;
+                const int gt = __builtin_amdgcn_readlane(my_g, uu);
+                if (gt != cur_g) {
+                    if (cur_g >= 0) flush();
+                    cur_g = gt;
+                    cur_jk = __builtin_amdgcn_readlane(my_jk, uu);
+                }
+                consume_one(Bt, u, uu, my_jo, acc);
+            }
+        };
+        bool staged = false;
+        int cb = 0;
+        do {
+            const int nt = max(0, min(JT_WAVE, n_my - cb));
+            const bool live = lane < nt;
+            int my_o = 0, my_g = 0, my_jk = 0;
+            if (live) {
+                const int t = cb + lane;
+                const int gi = t / nr;
+                my_g = gw0 + gi;
+                my_o = meta[it.o_kout_tile + my_g] + meta[rout_off + (t - gi * nr)];
+                my_jk = meta[it.o_kout_j + my_g];
+            }
+            const int my_jo = live ? meta[G.jout_off + my_o] : 0;
+            issue(A, 0, nt, my_o);
+            if (!staged) {
+                stage();
+                staged = true;
+            }
+            for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
+                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
+                consume_w(A, uq, nt, my_g, my_jk, my_jo);
+                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
+                if (uq + JT_UNROLL < nt) consume_w(B, uq + JT_UNROLL, nt, my_g, my_jk, my_jo);
+            }
+            cb += JT_WAVE;
+        } while (cb < n_my);
+        if (cur_g >= 0) flush();
+        return;
+    }
+
+    bool staged = false;
+    for (int g = task.g0; g < task.g1; ++g) {
+        int k = 0, sp = 0, q0, q1, tile_k = 0;
+        if (has_out) {
+            k = g / it.nsplit;
+            sp = g - k * it.nsplit;
+            q0 = sp * it.tpg;
+            q1 = min(q0 + it.tpg, it.o_n_rout);
+            tile_k = meta[it.o_kout_tile + k];
+        } else {
+            q0 = g * it.tpg;
+            q1 = min(q0 + it.tpg, it.n_tiles);
+        }
+        const int per = (q1 - q0 + JT_WAVES_PER_BLOCK - 1) / JT_WAVES_PER_BLOCK;
+        const int a = min(q1, q0 + wave * per), b = min(q1, a + per);
+#pragma unroll
+        for (int kk = 0; kk < JT_MS; ++kk)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[kk][q] = 0.f;
+        int cb = a;
+        do {
+            const int nt = max(0, min(JT_WAVE, b - cb));
+            const bool live = lane < nt;
+            int my_o = 0;
+            if (live) my_o = has_out ? tile_k + meta[rout_off + cb + lane] : cb + lane;
+            const int my_jo = live ? meta[G.jout_off + my_o] : 0;
+            issue(A, 0, nt, my_o);
+            if (!staged) {
+                stage();
+                staged = true;
+            }
+            for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
+                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
+                consume(A, uq, nt, my_jo, acc);
+                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
+                if (uq + JT_UNROLL < nt) consume(B, uq + JT_UNROLL, nt, my_jo, acc);
+            }
+            cb += JT_WAVE;
+        } while (cb < b);
+        if (!has_out) continue;
+        // per slot: the block's position sums (waves in order) into posk[k],
+        // then every wave folds the classes of its share of the slots
+#pragma unroll
+        for (int kk = 0; kk < JT_MS; ++kk) {
+            if (kk >= ns) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (valid[q]) L.red[wave][pos[q]] = acc[kk][q];
+            __syncthreads();
+            for (int t = threadIdx.x; t < T; t += JT_BLOCK)
+                posk[kk][t] = (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
+            __syncthreads();
+        }
+        const int jk = meta[it.o_kout_j + k];
+        for (int kk = wave; kk < ns; kk += JT_WAVES_PER_BLOCK)
+            fold_store(posk[kk], L, it.o_n_cls, it.o_m_in, partial + ms_part[kk] + (int64_t)sp * it.o_ssize + jk, lane);
+        __syncthreads();
     }
 }
 
@@ -778,6 +1051,78 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
     }
 }
 
+
+// Distribute messages with small separators and few partial rows are
+// finalized by a single wave (no block barriers): lane l owns separator
+// entries j = l + 64c.  Both pass kernels use this for exactly these
+// messages, so a slot's bits do not depend on which kernel ran its pass.
+#define JT_WFIN_MAX_SEP 255   // below the large-clique tree's smallest separators (256), where a block finalize is faster
+#define JT_WFIN_MAX_ROWS 4
+__device__ __forceinline__ bool wave_finalized(const JtMsg &m) {
+    return m.kind == JT_MSG_DIST && m.ssize <= JT_WFIN_MAX_SEP && m.nsplit <= JT_WFIN_MAX_ROWS;
+}
+
+//  1. raw[j] = ((0 + P[0][j]) + P[1][j]) + ... in row order;
+//  2. sigma = sum_j raw[j] in FP64: each lane its entries in ascending c,
+//     then a fixed wave tree;
+//  3. lane 0 updates the log-scales and the target's output scale;
+//  4. ratio[j] = (raw[j] * |S| / sigma) / old[j], 0 where old[j] = 0.
+__device__ __forceinline__ void wave_finalize_dist(const FinPtrs &F, const JtMsg &m, const FinScalars &fs, int slot,
+                                                   int lane) {
+    const int nc = F.n_cliques;
+    const float *P = F.partial + (int64_t)slot * F.partial_stride + m.partial_off;
+    float *raw = F.sep + (int64_t)slot * F.sep_stride + m.sepd_off;
+    const float *oldc = F.sep + coll_slot(F.cs_row, m.to, slot) * F.sep_stride + m.sepc_off;
+    double *lam = F.lam + (int64_t)slot * F.lam_stride;
+    float *scl = F.scale + (int64_t)slot * F.scale_stride;
+    const int ssize = m.ssize, nsplit = m.nsplit;
+    constexpr int C = (JT_WFIN_MAX_SEP + JT_WAVE - 1) / JT_WAVE;
+    float v[C], od[C];
+    double local = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = lane + JT_WAVE * c;
+        float x[JT_WFIN_MAX_ROWS];
+        od[c] = 0.f;
+        v[c] = 0.f;
+        if (JT_WAVE * c >= ssize) continue;      // uniform: no column of this round exists
+        const bool ok = j < ssize;
+#pragma unroll
+        for (int r = 0; r < JT_WFIN_MAX_ROWS; ++r) x[r] = (ok && r < nsplit) ? ldp(P + r * ssize + j) : 0.f;
+        od[c] = ok ? oldc[j] : 0.f;
+        float a = 0.f;
+#pragma unroll
+        for (int r = 0; r < JT_WFIN_MAX_ROWS; ++r)
+            if (r < nsplit) a += x[r];
+        v[c] = a;
+        if (ok) local += (double)a;
+    }
+    const double sigma = wave_sum_lane0(local);
+    float f = 0.f;
+    if (lane == 0) {
+        const double ns = (double)ssize;
+        const double logz = fs.l0;
+        double lsd = 0.0, fd = 0.0;
+        if (sigma > 0.0) {
+            fd = ns / sigma;
+            lsd = logz + log(sigma / ns);
+        }
+        lam[JT_LAM_SD(nc) + m.edge] = lsd;
+        const double lcal = fs.l1 + lsd - fs.l2;
+        scl[m.to] = (float)exp(lcal - logz);
+        f = (float)fd;
+    }
+    f = __shfl(f, 0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = lane + JT_WAVE * c;
+        if (JT_WAVE * c >= ssize) continue;
+        if (j < ssize) {
+            const float nw = v[c] * f;
+            raw[j] = (od[c] == 0.f) ? 0.f : nw / od[c];
+        }
+    }
+}
 }  // namespace
 
 // One launch = the passes of one tree level (or one message) for every slot.
@@ -794,7 +1139,7 @@ __device__ __forceinline__ void finalize_message(const FinPtrs &F, const JtMsg &
 // Work: a plain launch has n_tasks blocks per slot (block b: slot b / n_tasks,
 // task b % n_tasks).  A listed launch reads its (task, slot) entries from
 // `work`, one per block; its grid is at least the entry count (*work_count)
-// and the blocks beyond it return at once.
+// and the blocks beyond it, and padding entries (task -1), return at once.
 // Five waves per SIMD (five blocks per CU): the register budget that keeps
 // enough tile loads in flight per CU (measured: 4 waves per SIMD costs 5 % on
 // the large-clique tree and 10 % on the batched one).
@@ -817,7 +1162,7 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
             // the entry is read together with the count (the list holds
             // work_cap entries, so the read stays inside it either way)
             const JtWork e = work[w];
-            if (w >= *work_count) return;
+            if (w >= *work_count || e.task < 0) return;   // past the count, or per-XCD padding
             tix = e.task;
             slot = e.slot;
         } else {
@@ -920,10 +1265,119 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
 #if !JT_FS_EARLY
                 fs = load_fin_scalars(F, m, slot);
 #endif
-                finalize_message(F, m, fs, slot, L, lds_ratio, lds_floats);
+                if (wave_finalized(m)) {
+                    if (threadIdx.x < JT_WAVE) wave_finalize_dist(F, m, fs, slot, threadIdx.x);
+                } else {
+                    finalize_message(F, m, fs, slot, L, lds_ratio, lds_floats);
+                }
                 if (it.n_tasks > 1 && threadIdx.x == 0) *cnt = 0;    // ready for the next propagation
             }
         }
+    }
+}
+
+// Multi-slot distribute launch (four blocks per CU, each serving up to JT_MS
+// slots): entry e of `work` is (task, chunk): the task
+// of every slot of chunks[chunk] (up to JT_MS slots reading the same source
+// table).  task = -1 pads the per-XCD lists; such blocks return at once.
+// After the pass each slot of the set counts its arrival, and the block
+// finalizes the messages of the slots it arrived last for, one after the
+// other (same hand-off as the single-slot kernel).
+extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void jt_pass_multi_kernel(
+    const JtBlock *__restrict__ blocks, const int32_t *__restrict__ meta, const float *__restrict__ init,
+    const float *__restrict__ coll, float *__restrict__ out, float *__restrict__ sep, float *__restrict__ scale,
+    float *__restrict__ partial, const JtMsg *__restrict__ msgs, const int32_t *__restrict__ child_edges,
+    double *__restrict__ lam, int32_t *__restrict__ flag, int32_t *__restrict__ icnt,
+    const int32_t *__restrict__ csrc, const JtWork *__restrict__ work, const int32_t *__restrict__ work_count,
+    const JtChunk *__restrict__ chunks, PassStrides st, int64_t lam_stride, int64_t icnt_stride, int64_t csrc_stride,
+    int n_cliques, int task_begin, int lds_floats) {
+    extern __shared__ __align__(16) float lds_ratio[];
+    __shared__ PassLds L;
+    __shared__ float posk[JT_MS][JT_TILE_MAX];
+    __shared__ int64_t ms_part[JT_MS];
+    __shared__ int64_t ms_dst[JT_MS];
+    __shared__ float ms_scl[JT_MS];
+    __shared__ int32_t ms_slot[JT_MS];
+    __shared__ int32_t ms_last[JT_MS];
+    const int w = blockIdx.x;
+    const JtWork e = work[w];
+    if (w >= *work_count || e.task < 0) return;
+    const JtChunk chk = chunks[e.slot];
+    int ns = 0;
+#pragma unroll
+    for (int k = 0; k < JT_MS; ++k) ns += chk.s[k] >= 0 ? 1 : 0;
+    const JtBlock *__restrict__ rec = blocks + task_begin + e.task;
+    const JtItem it = rec->it;
+    const JtGather G = rec->g[0];
+    JtTask task;
+    task.item = rec->item;
+    task.g0 = rec->g0;
+    task.g1 = rec->g1;
+    task.pad = 0;
+    if (threadIdx.x < JT_MS) {
+        const int k = threadIdx.x;
+        const int32_t sk = chunks[e.slot].s[k];   // per-thread element: read from memory, not the register copy
+        ms_slot[k] = sk;
+        ms_part[k] = sk >= 0 ? (int64_t)sk * st.partial + it.partial_off : 0;
+        ms_dst[k] = sk >= 0 ? (int64_t)sk * st.out + it.dst_off : 0;
+        ms_scl[k] = sk >= 0 ? scale[(int64_t)sk * st.scale + it.scale_clique] : 0.f;
+    }
+    // every slot of the set reads the clique's collect data from the same
+    // (evidence-free) slot, or the shared initial table
+    const float *src = it.src_kind == JT_SRC_INIT
+                           ? init + it.src_off
+                           : coll + (int64_t)csrc[(int64_t)chk.s[0] * csrc_stride + it.clique] * st.coll + it.src_off;
+    __syncthreads();
+    if (it.vec == 4)
+        pass_multi<4>(it, task, ms_slot, ns, G, meta, src, out, sep, scale, partial, st, lds_ratio, L, posk, ms_part,
+                      ms_dst, ms_scl);
+    else
+        pass_multi<1>(it, task, ms_slot, ns, G, meta, src, out, sep, scale, partial, st, lds_ratio, L, posk, ms_part,
+                      ms_dst, ms_scl);
+    if (it.msg < 0) return;
+    const JtMsg m = msgs[it.msg];
+    wait_vm_stores();   // this wave's partials are acknowledged (see jt_pass_kernel)
+    __syncthreads();
+    if (threadIdx.x < ns) {
+        const int k = threadIdx.x;
+        ms_last[k] = it.n_tasks > 1
+                         ? atomicAdd(icnt + (int64_t)ms_slot[k] * icnt_stride + task.item, 1) == it.n_tasks - 1
+                         : 1;
+    }
+    __syncthreads();
+    FinPtrs F;
+    F.child_edges = child_edges;
+    F.partial = partial;
+    F.sep = sep;
+    F.lam = lam;
+    F.scale = scale;
+    F.flag = flag;
+    F.partial_stride = st.partial;
+    F.sep_stride = st.sep;
+    F.lam_stride = lam_stride;
+    F.scale_stride = st.scale;
+    F.n_cliques = n_cliques;
+    if (wave_finalized(m)) {
+        // one wave per slot, four slots at a time
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / JT_WAVE);
+        for (int k = wave; k < ns; k += JT_WAVES_PER_BLOCK) {
+            if (!ms_last[k]) continue;
+            const int slot = ms_slot[k];
+            F.cs_row = csrc + (int64_t)slot * csrc_stride;
+            const FinScalars fs = load_fin_scalars(F, m, slot);
+            wave_finalize_dist(F, m, fs, slot, threadIdx.x & (JT_WAVE - 1));
+            if (it.n_tasks > 1 && (threadIdx.x & (JT_WAVE - 1)) == 0) icnt[(int64_t)slot * icnt_stride + task.item] = 0;
+        }
+        return;
+    }
+    for (int k = 0; k < ns; ++k) {
+        if (!ms_last[k]) continue;
+        const int slot = ms_slot[k];
+        F.cs_row = csrc + (int64_t)slot * csrc_stride;
+        const FinScalars fs = load_fin_scalars(F, m, slot);
+        finalize_message(F, m, fs, slot, L, lds_ratio, lds_floats);
+        if (it.n_tasks > 1 && threadIdx.x == 0) icnt[(int64_t)slot * icnt_stride + task.item] = 0;
+        __syncthreads();
     }
 }
 
@@ -959,6 +1413,23 @@ hipError_t jt_launch_pass(const JtDev &d, int task_begin, int n_tasks, int n_slo
                        d.child_edges, d.lam, d.flag, d.icnt, d.csrc, listed ? d.work + work_off : nullptr,
                        listed ? d.work_count + work_idx : nullptr, st, d.lam_stride, d.icnt_stride, d.csrc_stride,
                        d.n_cliques, task_begin, n_tasks, n_tasks * n_slots, lds_floats, flags);
+    return hipGetLastError();
+}
+
+hipError_t jt_launch_pass_multi(const JtDev &d, int task_begin, int lds_floats, int64_t work_off, int work_idx,
+                                int grid, hipStream_t s) {
+    PassStrides st;
+    st.coll = d.coll_stride;
+    st.out = d.out_stride;
+    st.sep = d.sep_stride;
+    st.partial = d.partial_stride;
+    st.scale = d.scale_stride;
+    st.ev_idx = d.ev_idx_stride;
+    st.ev_ent = d.ev_ent_stride;
+    hipLaunchKernelGGL(jt_pass_multi_kernel, dim3((unsigned)grid), dim3(JT_BLOCK), (size_t)lds_floats * sizeof(float), s,
+                       d.blocks, d.meta, d.init, d.coll, d.out, d.sep, d.scale, d.partial, d.msgs, d.child_edges,
+                       d.lam, d.flag, d.icnt, d.csrc, d.work + work_off, d.work_count + work_idx, d.chunks, st,
+                       d.lam_stride, d.icnt_stride, d.csrc_stride, d.n_cliques, task_begin, lds_floats);
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <stdexcept>
 
 namespace jt {
 
@@ -462,17 +464,35 @@ bool verify_plan(const Plan &P, std::string &why) {
                 return bad("block gather copy");
     }
     {
-        int64_t wt = 0;
+        int64_t wt = 0, ct = 0;
         int32_t nl = 0;
         for (const Launch &l : P.fused) {
-            if (!l.listed) continue;
-            if (!P.share || !l.collect) return bad("listed launch outside a batched collect");
-            if (l.work_off != wt || l.work_cap != (int64_t)l.count * P.n_regions || l.work_idx != nl)
+            if (!l.listed) {
+                if (l.multi) return bad("multi-slot launch not listed");
+                continue;
+            }
+            if (!P.share) return bad("listed launch outside a batched tree");
+            const int64_t cap = l.multi ? 8 * (int64_t)l.chunk_cap
+                                        : 8 * (int64_t)l.count * (l.collect ? P.n_regions : P.n_slots);
+            if (l.work_off != wt || l.work_cap != cap || l.work_idx != nl || (l.multi && l.collect))
                 return bad("listed launch layout");
+            if (l.multi) {
+                if (l.chunk_off != ct || l.chunk_cap < 1) return bad("chunk layout");
+                ct += l.chunk_cap;
+                for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
+                    const int32_t i = P.tasks[t].item;
+                    if (!P.item_multi[i]) continue;
+                    const JtItem &it = P.items[i];
+                    const JtGather &G = P.gathers[it.gather_base];
+                    if (it.n_gather != 1 || G.src_clique != -1 || G.lds_off != 0 ||
+                        JT_MS * align_up(G.ssize, 4) > l.lds_floats || it.src_kind == JT_SRC_OUT)
+                        return bad("multi-slot item");
+                }
+            }
             wt += l.work_cap;
             ++nl;
         }
-        if (wt != P.work_total || nl != P.n_listed) return bad("work totals");
+        if (wt != P.work_total || nl != P.n_listed || ct != P.chunk_total) return bad("work totals");
     }
     for (const JtMsg &m : P.msgs) {
         if (m.ssize < 1 || m.nsplit < 1) return bad("message shape");
@@ -921,18 +941,66 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         }
     }
     P.bytes_fused = bytes;
-    // batched trees: the collect launches walk per-propagation work lists
-    // (the evidence-free slot's tasks plus the (task, slot) pairs whose
-    // clique has evidence below it), sized for every task of every region
+    // Batched trees: every fused launch walks a per-propagation work list.
+    //  * collect: the evidence-free slot's tasks plus the (task, slot) pairs
+    //    whose clique has evidence of that slot below it;
+    //  * distribute: a multi-slot launch over sets of up to JT_MS slots that
+    //    read the same evidence-free source table (one tile load serves them
+    //    all), then a launch over the remaining (task, slot) pairs.
+    // Lists are sized for the worst case (every task of every region; a
+    // multi-slot list also for its per-XCD padding).
+    P.item_multi.assign(P.items.size(), 0);
     if (P.share) {
-        for (Launch &l : P.fused) {
-            if (!l.collect || l.count == 0) continue;
+        for (const Launch &l : P.fused) {
+            if (l.collect || l.count == 0) continue;
+            for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
+                const int32_t i = P.tasks[t].item;
+                const JtItem &it = P.items[i];
+                if (it.n_gather != 1) continue;
+                const JtGather &G = P.gathers[it.gather_base];
+                if (G.src_clique != -1 || JT_MS * align_up(G.ssize, 4) > JT_LDS_RATIO_FLOATS) continue;
+                P.item_multi[i] = 1;
+            }
+        }
+        std::vector<Launch> L2;
+        const int64_t per_task_chunks = (P.n_slots + JT_MS - 1) / JT_MS;
+        for (Launch l : P.fused) {
+            if (l.count == 0) {
+                L2.push_back(l);
+                continue;
+            }
             l.listed = 1;
+            // lists hold 8 x the entries: room for the per-XCD padding
+            if (l.collect) {
+                l.work_cap = (int32_t)std::min<int64_t>(8 * (int64_t)l.count * P.n_regions, INT32_MAX);
+                if (8 * (int64_t)l.count * P.n_regions > l.work_cap) return fail(err, JT_E_TOO_LARGE, "work list too long");
+                L2.push_back(l);
+                continue;
+            }
+            int64_t eligible = 0;
+            for (int32_t t = l.begin; t < l.begin + l.count; ++t) eligible += P.item_multi[P.tasks[t].item];
+            if (eligible > 0) {
+                Launch m = l;
+                m.multi = 1;
+                if (eligible * per_task_chunks * 8 > INT32_MAX) return fail(err, JT_E_TOO_LARGE, "work list too long");
+                m.chunk_cap = (int32_t)(eligible * per_task_chunks);
+                m.work_cap = 8 * m.chunk_cap;
+                L2.push_back(m);
+            }
+            l.work_cap = (int32_t)std::min<int64_t>(8 * (int64_t)l.count * P.n_slots, INT32_MAX);
+            if (8 * (int64_t)l.count * P.n_slots > l.work_cap) return fail(err, JT_E_TOO_LARGE, "work list too long");
+            L2.push_back(l);
+        }
+        P.fused = L2;
+        for (Launch &l : P.fused) {
+            if (!l.listed) continue;
             l.work_off = P.work_total;
-            l.work_cap = (int32_t)std::min<int64_t>((int64_t)l.count * P.n_regions, std::numeric_limits<int32_t>::max());
-            if ((int64_t)l.count * P.n_regions > l.work_cap) return fail(err, JT_E_TOO_LARGE, "work list too long");
             l.work_idx = P.n_listed++;
             P.work_total += l.work_cap;
+            if (l.multi) {
+                l.chunk_off = P.chunk_total;
+                P.chunk_total += l.chunk_cap;
+            }
         }
     }
 
@@ -1048,6 +1116,10 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
                 const JtItem &it = P.items[P.tasks[t].item];
                 l.lds_floats = std::max<int32_t>(l.lds_floats, it.lds_floats);
+                // a multi-slot pass stages one ratio table per slot of its set
+                if (l.multi && P.item_multi[P.tasks[t].item])
+                    l.lds_floats = std::max<int32_t>(
+                        l.lds_floats, JT_MS * (int32_t)align_up(P.gathers[it.gather_base].ssize, 4));
                 // room to stage a finalized separator of up to JT_FIN_STAGE_FLOATS entries
                 if (it.msg >= 0)
                     l.lds_floats = std::max<int32_t>(l.lds_floats, std::min<int32_t>(JT_FIN_STAGE_FLOATS, it.o_ssize));
@@ -1056,7 +1128,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
         }
     for (std::vector<Launch> *L : {&P.fused, &P.plain})
         for (Launch &l : *L) {
-            if (l.is_pass != 1 || l.count == 0) continue;
+            if (l.is_pass != 1 || l.count == 0 || l.multi) continue;
             int32_t last = -1;
             for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
                 const int32_t i = P.tasks[t].item;
@@ -1130,6 +1202,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.off_csrc = region(S * (size_t)P.csrc_stride * sizeof(int32_t));
     P.off_work_count = region(std::max<size_t>(1, (size_t)P.n_listed) * sizeof(int32_t));
     P.off_work = region(std::max<size_t>(1, (size_t)P.work_total) * sizeof(JtWork));
+    P.off_chunks = region(std::max<size_t>(1, (size_t)P.chunk_total) * sizeof(JtChunk));
     P.off_dyn = P.off_ev_idx;
     P.dyn_bytes = off - P.off_ev_idx;
     P.icnt_stride = align_up(std::max<int64_t>(1, (int64_t)P.items.size()), kAlignFloats);
@@ -1145,6 +1218,46 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     if (!verify_plan(P, why)) return fail(err, JT_E_ARG, why);
     return JT_OK;
 }
+
+namespace {
+
+// Deal groups of work entries to the 8 XCDs (blocks go to the XCDs round
+// robin, so entry e of a list runs on XCD e % 8): a group's entries share a
+// table (the same clique's source or absorbed table), so keeping them on one
+// XCD keeps that table in one L2.  Groups are taken largest first onto the
+// least-loaded XCD; a group above an eighth of the launch's work is cut so
+// that one large clique still spreads over the chip.  Returns the list
+// length (8 x the longest queue); shorter queues are padded with task -1.
+int32_t place_on_xcds(std::vector<std::vector<JtWork>> &groups, const std::vector<int64_t> &weight, JtWork *out) {
+    int64_t total = 0;
+    for (int64_t w : weight) total += std::max<int64_t>(1, w);
+    const int64_t cap = std::max<int64_t>(1, (total + 7) / 8);
+    struct G { int64_t w; size_t g, lo, hi; };
+    std::vector<G> parts;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const size_t n = groups[g].size();
+        if (n == 0) continue;
+        const int64_t w = std::max<int64_t>(1, weight[g]);
+        const size_t pieces = (size_t)std::min<int64_t>((int64_t)n, (w + cap - 1) / cap);
+        for (size_t k = 0; k < pieces; ++k)
+            parts.push_back({w / (int64_t)pieces, g, n * k / pieces, n * (k + 1) / pieces});
+    }
+    std::stable_sort(parts.begin(), parts.end(), [](const G &a, const G &b) { return a.w > b.w; });
+    std::vector<std::vector<JtWork>> q(8);
+    std::vector<int64_t> load(8, 0);
+    for (const G &p : parts) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (size_t i = p.lo; i < p.hi; ++i) q[x].push_back(groups[p.g][i]);
+        load[x] += p.w;
+    }
+    size_t len = 0;
+    for (const auto &v : q) len = std::max(len, v.size());
+    for (size_t k = 0; k < len; ++k)
+        for (int x = 0; x < 8; ++x) out[8 * k + x] = k < q[x].size() ? q[x][k] : JtWork{-1, 0};
+    return (int32_t)(8 * len);
+}
+
+}  // namespace
 
 void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_vars, int32_t n_active, Dynamic &D) {
     const int32_t nc = P.n_cliques, S = P.n_slots, N = P.n_slots;   // N: the evidence-free slot
@@ -1181,25 +1294,104 @@ void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_va
             for (int32_t c = 0; c < nc; ++c)
                 if (!dirty[s][c]) D.csrc[(size_t)s * P.csrc_stride + c] = N;
     auto runs = [&](int32_t s, int32_t c) { return share ? (s == N || dirty[s][c]) : s < n_active; };
+    // a distribute pass of slot s reads the evidence-free slot's table
+    auto shared_src = [&](int32_t s, int32_t c) { return D.csrc[(size_t)s * P.csrc_stride + c] != s; };
+    JtChunk none;
+    for (int k = 0; k < JT_MS; ++k) none.s[k] = -1;
+    D.chunks.assign((size_t)std::max<int64_t>(1, P.chunk_total), none);
     int64_t bytes = 0;
     for (const Launch &l : P.fused) {
         if (l.count == 0) continue;
-        // slots that execute each task of the launch
-        if (l.listed) {
-            int32_t k = 0;
+        if (l.listed && l.multi) {
+            // sets of up to JT_MS slots per (task, clique without evidence of
+            // them); all sets of one task go to one XCD (blocks are dealt to
+            // the XCDs round robin, so entry e runs on XCD e % 8), which keeps
+            // the shared source table in that XCD's L2; tasks are spread over
+            // the XCDs by their work, the lists padded to equal length
+            struct Ent { int32_t task, chunk; };
+            std::vector<std::vector<Ent>> xl(8);
+            std::vector<int64_t> load(8, 0);
+            int64_t nch = 0;
+            std::vector<std::pair<int64_t, int32_t>> order;
             for (int32_t t = 0; t < l.count; ++t) {
-                const int32_t c = P.items[P.tasks[l.begin + t].item].clique;
-                if (share) D.work[l.work_off + k++] = JtWork{t, N};
-                for (int32_t s = 0; s < n_active; ++s)
-                    if (runs(s, c)) D.work[l.work_off + k++] = JtWork{t, s};
+                const int32_t i = P.tasks[l.begin + t].item;
+                if (!P.item_multi[i]) continue;
+                const JtTask &T = P.tasks[l.begin + t];
+                order.push_back({-(16384 + (int64_t)(T.g1 - T.g0) * P.items[i].tpg * P.items[i].T), t});
             }
+            std::stable_sort(order.begin(), order.end());
+            for (const auto &ot : order) {
+                const int32_t t = ot.second;
+                const int32_t c = P.items[P.tasks[l.begin + t].item].clique;
+                std::vector<int32_t> sl;
+                if (share)
+                    for (int32_t s = 0; s < n_active; ++s)
+                        if (shared_src(s, c)) sl.push_back(s);
+                if (sl.empty()) continue;
+                const int32_t x = (int32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (size_t k0 = 0; k0 < sl.size(); k0 += JT_MS) {
+                    JtChunk ch;
+                    for (int k = 0; k < JT_MS; ++k) ch.s[k] = k0 + k < sl.size() ? sl[k0 + k] : -1;
+                    D.chunks[l.chunk_off + nch] = ch;
+                    xl[x].push_back({t, (int32_t)nch});
+                    ++nch;
+                }
+                load[x] += -ot.first * (int64_t)((sl.size() + JT_MS - 1) / JT_MS);
+            }
+            size_t len = 0;
+            for (const auto &v : xl) len = std::max(len, v.size());
+            for (size_t k = 0; k < len; ++k)
+                for (int x = 0; x < 8; ++x)
+                    D.work[l.work_off + 8 * k + x] = k < xl[x].size() ? JtWork{xl[x][k].task, (int32_t)l.chunk_off + xl[x][k].chunk}
+                                                                     : JtWork{-1, 0};
+            const int32_t k = (int32_t)(8 * len);
             D.count[l.work_idx] = k;
             int64_t g = 1;
             while (g < k) g *= 2;
-            D.grid[l.work_idx] = (int32_t)std::min<int64_t>(g, l.work_cap);
+            D.grid[l.work_idx] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g, l.work_cap));
+            continue;   // its bytes are counted with the level's other launch
+        }
+        if (l.listed) {
+            // groups: collect -- every pass of one clique (they read its
+            // initial table); distribute -- the passes of one (clique, slot)
+            // (the items of its children read its table once each)
+            std::map<std::pair<int32_t, int32_t>, size_t> gid;
+            std::vector<std::vector<JtWork>> groups;
+            std::vector<int64_t> weight;
+            auto put = [&](int32_t c, int32_t key, int32_t t, int32_t s) {
+                auto it = gid.emplace(std::make_pair(c, key), groups.size());
+                if (it.second) {
+                    groups.emplace_back();
+                    weight.push_back(0);
+                }
+                groups[it.first->second].push_back(JtWork{t, s});
+                // a block costs its set-up and finalize latency plus its
+                // streaming: weigh it as a fixed 16K entries plus its entries
+                const JtTask &T = P.tasks[l.begin + t];
+                weight[it.first->second] += 16384 + (int64_t)(T.g1 - T.g0) * P.items[T.item].tpg * P.items[T.item].T;
+            };
+            for (int32_t t = 0; t < l.count; ++t) {
+                const int32_t i = P.tasks[l.begin + t].item;
+                const int32_t c = P.items[i].clique;
+                if (l.collect) {
+                    if (share) put(c, -1, t, N);
+                    for (int32_t s = 0; s < n_active; ++s)
+                        if (runs(s, c)) put(c, -1, t, s);
+                } else {
+                    // the pairs no multi-slot set took
+                    for (int32_t s = 0; s < n_active; ++s)
+                        if (!(share && P.item_multi[i] && shared_src(s, c))) put(c, s, t, s);
+                }
+            }
+            const int32_t k = place_on_xcds(groups, weight, &D.work[l.work_off]);
+            if (k > l.work_cap) throw std::logic_error("work list overflow");
+            D.count[l.work_idx] = k;
+            int64_t g = 1;
+            while (g < k) g *= 2;
+            D.grid[l.work_idx] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g, l.work_cap));
         }
         // FP32 table bytes: shared tables (initial tables, evidence-free
-        // absorbed tables) once per launch, slot tables per slot
+        // absorbed tables) once per level, slot tables per slot
         int32_t last = -1;
         for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
             const int32_t i = P.tasks[t].item;
@@ -1222,7 +1414,7 @@ void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_va
                     int64_t own = 0;
                     bool any_shared = false;
                     for (int32_t s = 0; s < n_active; ++s) {
-                        if (D.csrc[(size_t)s * P.csrc_stride + c] == s) ++own;
+                        if (!shared_src(s, c)) ++own;
                         else any_shared = true;
                     }
                     bytes += tb * (own + (any_shared ? 1 : 0));
@@ -1233,6 +1425,114 @@ void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_va
     }
     D.bytes = bytes;
     (void)S;
+}
+
+void build_paper_plan(const Plan &P, PaperPlan &pp) {
+    pp = PaperPlan();
+    const int32_t nc = P.n_cliques;
+    // the caller's orientation: children ascending
+    std::vector<std::vector<int32_t>> ch(nc);
+    for (int32_t c = 0; c < nc; ++c)
+        if (P.parent[c] >= 0) ch[P.parent[c]].push_back(c);
+    std::vector<int64_t> mu_off_side(2 * (size_t)nc, -1);   // per edge: child-side and parent-side lists
+    auto lists = [&](int32_t e, int side) {
+        int64_t &o = mu_off_side[2 * (size_t)e + side];
+        if (o < 0) {
+            o = pp.mu_total;
+            pp.mu_total += P.cl[side == 0 ? e : P.parent[e]].size;
+        }
+        return o;
+    };
+    auto add = [&](int32_t e, int32_t from, int32_t to) {
+        JtPaperMsg m;
+        std::memset(&m, 0, sizeof(m));
+        const int fs = from == e ? 0 : 1, ts = to == e ? 0 : 1;
+        m.mu_from = lists(e, fs);
+        m.mu_to = lists(e, ts);
+        m.ssize = (int32_t)P.edge[e].ssize;
+        m.m_from = (int32_t)(P.cl[from].size / m.ssize);
+        m.m_to = (int32_t)(P.cl[to].size / m.ssize);
+        m.from_off = P.cl[from].out_off;
+        m.to_off = P.cl[to].out_off;
+        m.edge = e;
+        m.from = from;
+        m.to = to;
+        m.sepc_off = P.edge[e].sepc_off;
+        m.sepd_off = P.edge[e].sepd_off;
+        pp.msgs.push_back(m);
+    };
+    // Algorithm 2: a child's subtree is collected, then the child sends to
+    // its parent (post-order); Algorithm 3: a parent sends to each child,
+    // then the child distributes (pre-order)
+    {
+        std::vector<std::pair<int32_t, size_t>> st{{P.user_root, 0}};
+        while (!st.empty()) {
+            auto &top = st.back();
+            if (top.second < ch[top.first].size()) {
+                const int32_t c = ch[top.first][top.second++];
+                st.push_back({c, 0});
+            } else {
+                const int32_t c = top.first;
+                st.pop_back();
+                if (P.parent[c] >= 0) add(c, c, P.parent[c]);
+            }
+        }
+        std::vector<std::pair<int32_t, size_t>> st2{{P.user_root, 0}};
+        while (!st2.empty()) {
+            auto &top = st2.back();
+            if (top.second < ch[top.first].size()) {
+                const int32_t c = ch[top.first][top.second++];
+                add(c, top.first, c);
+                st2.push_back({c, 0});
+            } else {
+                st2.pop_back();
+            }
+        }
+    }
+    for (int32_t c = 0; c < nc; ++c)
+        for (int64_t a = 0; a < P.cl[c].size; a += 4096) {
+            JtPaperBlk b;
+            b.clique = c;
+            b.T = P.cl[c].T;
+            b.start = a;
+            b.end = std::min<int64_t>(P.cl[c].size, a + 4096);
+            b.init_off = P.cl[c].init_off;
+            b.out_off = P.cl[c].out_off;
+            pp.blocks.push_back(b);
+        }
+    size_t off = 0;
+    auto region = [&](size_t bytes) {
+        const size_t o = off;
+        off = (size_t)align_up((int64_t)(off + bytes), 256);
+        return o;
+    };
+    pp.off_msgs = region(std::max<size_t>(1, pp.msgs.size()) * sizeof(JtPaperMsg));
+    pp.off_blocks = region(std::max<size_t>(1, pp.blocks.size()) * sizeof(JtPaperBlk));
+    pp.off_mu = region(std::max<int64_t>(1, pp.mu_total) * sizeof(int32_t));
+    pp.bytes = off;
+}
+
+void paper_mu_lists(const Plan &P, const PaperPlan &pp, int32_t layout, int32_t *out) {
+    std::vector<char> done((size_t)std::max<int64_t>(1, pp.mu_total), 0);
+    std::vector<int32_t> map;
+    for (const JtPaperMsg &m : pp.msgs) {
+        for (int side = 0; side < 2; ++side) {
+            const int64_t base = side == 0 ? m.mu_from : m.mu_to;
+            if (done[base]) continue;
+            done[base] = 1;
+            const int32_t c = side == 0 ? m.from : m.to;
+            const int32_t e = m.edge;
+            const int32_t view = c == e ? P.edge[e].view_child : P.edge[e].view_parent;
+            const int64_t n = P.cl[c].size, S = m.ssize, len = n / S;
+            map.resize(n);
+            expand_map(P, view, map.data());
+            std::vector<int64_t> fill(S, 0);
+            for (int64_t r = 0; r < n; ++r) {   // ascending r: every list in ascending order
+                const int64_t j = map[r], k = fill[j]++;
+                out[base + (layout == JT_LAYOUT_INTERLEAVED_ ? k * S + j : j * len + k)] = (int32_t)r;
+            }
+        }
+    }
 }
 
 void evidence_tables(const Plan &P, const std::vector<int32_t> &vars, const std::vector<int32_t> &states,

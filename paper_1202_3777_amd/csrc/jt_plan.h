@@ -58,6 +58,9 @@ struct Launch {
     int32_t work_cap = 0;   // entries the list can hold: count * (slots + 1)
     int32_t work_idx = 0;   // its counter in the work-count array
     int32_t collect = 0;    // 1: a collect-sweep launch of the fused schedule
+    int32_t multi = 0;      // 1: multi-slot distribute launch (entries index JtChunk sets)
+    int64_t chunk_off = 0;  // its first chunk in the chunk region
+    int32_t chunk_cap = 0;
 };
 
 struct Plan {
@@ -103,6 +106,8 @@ struct Plan {
     int32_t n_regions = 1;           // slot regions: n_slots + share
     int32_t n_listed = 0;            // listed launches (work counters)
     int64_t work_total = 0;          // entries of all listed launches
+    int64_t chunk_total = 0;         // slot sets of all multi-slot launches
+    std::vector<char> item_multi;    // per item: eligible for multi-slot passes
     // per-slot region sizes (elements)
     int64_t csrc_stride = 0;
     int64_t init_floats = 0, coll_stride = 0, out_stride = 0, sep_stride = 0,
@@ -113,6 +118,7 @@ struct Plan {
            off_msgs = 0, off_child = 0, off_init = 0, off_coll = 0, off_out = 0, off_sep = 0,
            off_partial = 0, off_lam = 0, off_scale = 0, off_flag = 0, off_ev_idx = 0,
            off_ev_ent = 0, off_icnt = 0, off_csrc = 0, off_work = 0, off_work_count = 0, off_cltab = 0,
+           off_chunks = 0,
            total_bytes = 0;
     // the part of the workspace rewritten when evidence or the active slot
     // count change (evidence tables, collect sources, work lists): one range
@@ -125,6 +131,21 @@ struct Plan {
     int64_t bytes_fused = 0, bytes_plain = 0;   // all slots; shared initial tables counted once
 };
 
+// Paper-faithful schedule of a compiled tree (host side): messages in the
+// order of Algorithms 2-3 on the caller's root, children ascending, and the
+// per-entry blocks of the reset and normalization kernels.
+struct PaperPlan {
+    std::vector<JtPaperMsg> msgs;
+    std::vector<JtPaperBlk> blocks;
+    int64_t mu_total = 0;                 // int32 entries of all mapping lists
+    size_t off_msgs = 0, off_blocks = 0, off_mu = 0, bytes = 0;
+};
+void build_paper_plan(const Plan &plan, PaperPlan &pp);
+// The mapping lists of every message's two tables in `layout`
+// (JT_LAYOUT_NAIVE_ or JT_LAYOUT_INTERLEAVED_), concatenated as the
+// messages' mu_from / mu_to offsets say.
+void paper_mu_lists(const Plan &plan, const PaperPlan &pp, int32_t layout, int32_t *out);
+
 // Build the plan; returns JT_OK or an error code with `err` filled in.
 jt_status compile_plan(const jt_tree_desc *desc, Plan &plan, std::string &err);
 
@@ -133,6 +154,7 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &plan, std::string &err);
 struct Dynamic {
     std::vector<int32_t> csrc;          // [n_regions][csrc_stride]
     std::vector<JtWork> work;           // [work_total]
+    std::vector<JtChunk> chunks;        // [chunk_total]
     std::vector<int32_t> count;         // [n_listed]
     std::vector<int32_t> grid;          // [n_listed] blocks launched: the count rounded up to a power of
                                         // two (at most the list's capacity), so few graphs cover many counts

@@ -84,6 +84,8 @@ jt_status jt_propagate_scratch(jt_tree t, const float *init_potentials, float *p
         if (P.share && fused) jt::build_dynamic(P, t->ev_vars, P.n_slots, t->sx_dyn);
     } catch (const std::bad_alloc &) {
         return set_err(JT_E_NO_MEM, "host allocation failed");
+    } catch (const std::exception &x) {
+        return set_err(JT_E_ARG, std::string("schedule: ") + x.what());
     }
     auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
         if (n == 0) return hipSuccess;
@@ -95,6 +97,8 @@ jt_status jt_propagate_scratch(jt_tree t, const float *init_potentials, float *p
         e = up(P.off_csrc, t->sx_dyn.csrc.data(), t->sx_dyn.csrc.size() * sizeof(int32_t));
         if (e == hipSuccess) e = up(P.off_work_count, t->sx_dyn.count.data(), t->sx_dyn.count.size() * sizeof(int32_t));
         if (e == hipSuccess) e = up(P.off_work, t->sx_dyn.work.data(), t->sx_dyn.work.size() * sizeof(JtWork));
+        if (e == hipSuccess && P.chunk_total > 0)
+            e = up(P.off_chunks, t->sx_dyn.chunks.data(), t->sx_dyn.chunks.size() * sizeof(JtChunk));
     }
     if (e != hipSuccess) return hip_err(e, "scratch evidence upload");
     if (jt_status rc = enqueue(t, d, fused ? P.fused : P.plain, P.n_slots, fused, s, &t->sx_dyn.grid)) return rc;

@@ -312,3 +312,32 @@ def make_serving_trees(seed: int = 0, n_trees: int = 16, lo: float = 1e3,
                               clique_vars=flat, parent=parent, potentials=pot,
                               table_off=table_off, evidence=[]))
     return trees
+
+
+def make_separator_sweep(sep_vars: int, seed: int = 0, n_cliques: int = 40, fresh: int = 4,
+                         card: int = 2, n_obs: int = 2) -> Instance:
+    """A tree whose separators all have ``sep_vars`` variables of
+    cardinality ``card`` (|phi_S| = card**sep_vars) and whose cliques add
+    ``fresh`` variables each: the family over which the speedup is plotted
+    against the average separator size (the paper's Fig. 6 ordering)."""
+    rng = _rng(seed)
+    size = sep_vars + fresh
+    card_l: List[int] = [card] * size
+    cvars: List[List[int]] = [[int(x) for x in rng.permutation(size)]]
+    parent = np.full(n_cliques, -1, dtype=np.int32)
+    for c in range(1, n_cliques):
+        p = int(rng.integers(0, c))
+        parent[c] = p
+        pv = cvars[p]
+        sep = [pv[i] for i in sorted(rng.choice(len(pv), size=sep_vars, replace=False))]
+        new = list(range(len(card_l), len(card_l) + fresh))
+        card_l.extend([card] * fresh)
+        vs = sep + new
+        cvars.append([vs[i] for i in rng.permutation(len(vs))])
+    card_a = np.asarray(card_l, dtype=np.int32)
+    table_off = _table_offsets(card_a, cvars)
+    pot = _draw_potentials(rng, card_a, cvars, table_off, ("uniform", 0.1, 1.0))
+    ev = draw_evidence(rng, card_a, (n_obs, n_obs), 1)
+    off, flat = _pack(cvars)
+    return Instance(name=f"sepsweep{sep_vars}", seed=seed, card=card_a, clique_off=off, clique_vars=flat,
+                    parent=parent, potentials=pot, table_off=table_off, evidence=ev)

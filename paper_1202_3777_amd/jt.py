@@ -29,7 +29,13 @@ JT_MODE_FUSED = 0
 JT_MODE_GRAPH = 1
 JT_MODE_PLAIN = 2
 JT_MODE_DATAFLOW = 3
-MODES = {"fused": JT_MODE_FUSED, "graph": JT_MODE_GRAPH, "plain": JT_MODE_PLAIN, "dataflow": JT_MODE_DATAFLOW}
+JT_MODE_PAPER = 4
+JT_MODE_PAPER_GRAPH = 5
+MODES = {"fused": JT_MODE_FUSED, "graph": JT_MODE_GRAPH, "plain": JT_MODE_PLAIN, "dataflow": JT_MODE_DATAFLOW,
+         "paper": JT_MODE_PAPER, "paper_graph": JT_MODE_PAPER_GRAPH}
+JT_LAYOUT_NAIVE = 0
+JT_LAYOUT_INTERLEAVED = 1
+LAYOUTS = {"naive": JT_LAYOUT_NAIVE, "interleaved": JT_LAYOUT_INTERLEAVED}
 
 JT_Q_N_SLOTS = 0
 JT_Q_TOTAL_ENTRIES = 1
@@ -55,7 +61,7 @@ JT_Q_LAST_SHARED = 20
 JT_Q_LAST_COLLECT_PASSES = 21
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
-            "jt_marginals_all", "jt_read_out", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
+            "jt_marginals_all", "jt_read_out", "jt_paper_bytes", "jt_paper_bind", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
             "jt_propagate_scratch", "jt_free", "jt_last_error"]
 
 
@@ -108,9 +114,11 @@ def load():
     lib.jt_profile.argtypes = [V, I32, PD, PD, P32, P32]
     lib.jt_propagate_scratch.argtypes = [V, V, V, V, I32, V]
     lib.jt_read_out.argtypes = [V, I32, I32, V, V]
+    lib.jt_paper_bytes.argtypes = [V, ctypes.POINTER(SZ)]
+    lib.jt_paper_bind.argtypes = [V, V, SZ, I32, I32]
     for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
               "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
-              "jt_propagate_scratch", "jt_read_out"):
+              "jt_propagate_scratch", "jt_read_out", "jt_paper_bytes", "jt_paper_bind"):
         getattr(lib, f).restype = I32
     lib.jt_free.argtypes = [V]
     lib.jt_free.restype = None
@@ -193,6 +201,17 @@ def jt_marginals_all(h, slot: int, out_ptr: Optional[int]) -> float:
 def jt_read_out(h, slot0: int, n: int, posteriors_ptr: int, log_z_ptr: int):
     _check(load().jt_read_out(h, int(slot0), int(n), ctypes.c_void_p(posteriors_ptr), ctypes.c_void_p(log_z_ptr)),
            "jt_read_out")
+
+
+def jt_paper_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _check(load().jt_paper_bytes(h, ctypes.byref(n)), "jt_paper_bytes")
+    return int(n.value)
+
+
+def jt_paper_bind(h, workspace_ptr: int, nbytes: int, layout: int, threads_per_block: int):
+    _check(load().jt_paper_bind(h, ctypes.c_void_p(workspace_ptr), nbytes, int(layout), int(threads_per_block)),
+           "jt_paper_bind")
 
 
 def jt_query(h, what: int, arg: int = 0) -> int:
@@ -328,6 +347,16 @@ class JunctionTree(JunctionTreePlan):
 
     def profile(self, mode: str = "fused"):
         return jt_profile(self.handle, MODES[mode])
+
+    def paper_bind(self, layout: str = "interleaved", threads_per_block: int = 128):
+        """Mapping lists for the paper-faithful schedule (modes "paper" and
+        "paper_graph"), in a torch-owned workspace of their own."""
+        if getattr(self, "paper_workspace", None) is None:
+            with self.torch.cuda.stream(self.stream):
+                self.paper_workspace = self.torch.empty(jt_paper_bytes(self.handle), dtype=self.torch.uint8,
+                                                        device=self.device)
+        jt_paper_bind(self.handle, self.paper_workspace.data_ptr(), self.paper_workspace.numel(), LAYOUTS[layout],
+                      threads_per_block)
 
     def marginal(self, slot: int, clique: int) -> Tuple[np.ndarray, float]:
         out = np.empty(int(self.table_size[clique]), dtype=np.float32)

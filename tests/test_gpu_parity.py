@@ -307,3 +307,32 @@ def test_propagate_active_prefix():
         assert ei.value.code == jt.JT_E_STATE
     with pytest.raises(jt.JTError):
         tree.propagate("graph", n_active=5)
+
+
+def test_paper_schedule_parity_and_layouts():
+    # the paper's own kernel design (one thread per separator entry over
+    # explicit mapping lists, one message at a time): against the oracle,
+    # and bit-identical between the naive and interleaved layouts, across
+    # block sizes and between eager launches and a captured graph
+    jt = _gpu()
+    cases = [make_instance("c1", 0), make_instance("c4", 2, n_slots=3), make_instance("c2", 1, n_cliques=6),
+             make_instance("c3", 1, n_cliques=6),
+             from_arrays([257, 2, 1, 3, 5, 7], [[0, 1], [1, 2, 3], [3, 4, 5], [5]], [-1, 0, 1, 2], seed=1,
+                         evidence=[([0, 4], [200, 3])]),
+             from_arrays([2, 3, 4], [[0, 1], [2]], [-1, 0], seed=2, evidence=[([2], [1])])]
+    for inst in cases:
+        plan = oracle.Plan.from_instance(inst)
+        tree = jt.JunctionTree.from_instance(inst)
+        tree.paper_bind("naive", 64)
+        tree.propagate("paper")
+        first = []
+        for s in range(tree.n_slots):
+            compare(tree, plan, inst, s, plan.run(inst.potentials, *inst.evidence[s]), f"{inst.name}/paper-naive")
+            first.append(tree.marginals_all(s))
+        for layout, tpb, mode in (("interleaved", 256, "paper"), ("interleaved", 32, "paper_graph"),
+                                  ("naive", 512, "paper_graph")):
+            tree.paper_bind(layout, tpb)
+            tree.propagate(mode)
+            for s in range(tree.n_slots):
+                a, la = tree.marginals_all(s)
+                assert np.array_equal(a, first[s][0]) and la == first[s][1], (inst.name, layout, tpb, mode)
