@@ -209,6 +209,70 @@ jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z);
 jt_status jt_paper_bytes(jt_tree t, size_t *bytes);
 jt_status jt_paper_bind(jt_tree t, void *workspace, size_t bytes, int32_t layout, int32_t threads_per_block);
 
+/* Bayesian-network front end (Sec. 2.1: a junction tree is compiled from a
+ * Bayesian network by moralization and triangulation; Algorithm 4's
+ * Initialization multiplies the conditional tables into the cliques).
+ *   jt_bn_desc      variables 0..n_vars-1 with card[v] states; variable v's
+ *                   parents are parents[parent_off[v] .. parent_off[v+1]) and
+ *                   its conditional table P(v | parents) is laid out as
+ *                   (parents in that order..., v), last fastest, |table| =
+ *                   product of the cards; the tables of all variables are
+ *                   concatenated in variable order.
+ *   jt_compile_bn   validate (parents in range, no cycle), moralize,
+ *                   triangulate (greedy elimination, fewest fill-in edges,
+ *                   ties to fewer neighbours, then the lower id), keep the
+ *                   maximal cliques (each lists its variables ascending), join
+ *                   them by a maximum-weight spanning tree over separator
+ *                   sizes (ties to the lower clique ids; components joined by
+ *                   empty separators), root at clique 0, assign each family
+ *                   to the lowest-id clique holding it, and compile the tree
+ *                   as jt_compile_index_maps does (n_slots, tuning as there).
+ *                   *n_cliques receives the clique count.
+ *   jt_bn_structure the compiled tree: clique_off [n_cliques + 1],
+ *                   clique_vars [clique_off[n_cliques]], parent [n_cliques],
+ *                   family_clique [n_vars] (host arrays, caller-sized: query
+ *                   the clique count first, then JT_Q_TOTAL_CLIQUE_VARS).
+ *   jt_bind_bn      jt_bind, with the initial tables computed on the device
+ *                   from the conditional tables (`cpts`, device pointer, read
+ *                   during the call: it synchronizes the stream): each
+ *                   clique's table is the product, in ascending variable
+ *                   order, of the tables of the families assigned to it (1
+ *                   where none is).
+ *   jt_bn_expected_counts  after a propagation of slots [0, n_active): for
+ *                   every variable the expected counts of its family,
+ *                   sum over the slots of P(v, parents | e_slot), in the
+ *                   conditional table's layout, concatenated like the
+ *                   tables (`counts`, device pointer, FP32; each entry summed
+ *                   in FP64, slots in order).  Asynchronous on the bound
+ *                   stream.  The E-step of EM over a batch of evidence sets.
+ *   jt_bn_m_step    the M-step: every row of every conditional table (the
+ *                   card[v] entries of one parent configuration) becomes
+ *                   (counts + alpha) / sum over the row of (counts + alpha),
+ *                   into `cpts` (device pointers; alpha >= 0 is a Dirichlet
+ *                   pseudo-count; a row with zero sum becomes uniform).
+ *                   Asynchronous.
+ *   jt_bn_set_cpts  recompute the initial tables from new conditional tables
+ *                   (device pointer, read by the stream before the next
+ *                   propagation); asynchronous, like jt_bind_bn's product.
+ * Errors: JT_E_ARG, JT_E_NOT_JUNCTION_TREE (a cycle among the parents),
+ * JT_E_TOO_LARGE (a clique table of 2^31 entries or more), JT_E_NO_MEM,
+ * JT_E_STATE (not a network tree, or nothing propagated), JT_E_HIP. */
+typedef struct {
+    int32_t n_vars;
+    const int32_t *card;
+    const int64_t *parent_off;  /* [n_vars + 1] */
+    const int32_t *parents;     /* [parent_off[n_vars]] */
+    int32_t n_slots;
+    const jt_tuning *tuning;
+} jt_bn_desc;
+jt_status jt_compile_bn(const jt_bn_desc *bn, jt_tree *out, size_t *device_bytes, int32_t *n_cliques);
+jt_status jt_bn_structure(jt_tree t, int64_t *clique_off, int32_t *clique_vars, int32_t *parent,
+                          int32_t *family_clique);
+jt_status jt_bind_bn(jt_tree t, void *workspace, size_t bytes, const float *cpts, void *hip_stream);
+jt_status jt_bn_expected_counts(jt_tree t, int32_t n_active, float *counts);
+jt_status jt_bn_m_step(jt_tree t, const float *counts, float alpha, float *cpts);
+jt_status jt_bn_set_cpts(jt_tree t, const float *cpts);
+
 /* Asynchronous read-out on the bound stream: the posteriors of slots
  * [slot0, slot0 + n) packed in clique order, slot after slot
  * (n * sum |phi_X| floats), and their log Z_e (n doubles, -inf where the
@@ -262,7 +326,10 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *   JT_Q_LAST_SHARED (1 when the last propagation computed the evidence-free
  *     collect messages once and shared them, see jt_propagate),
  *   JT_Q_LAST_COLLECT_PASSES ((clique, slot) collect passes it ran, the
- *     evidence-free slot included).
+ *     evidence-free slot included),
+ *   JT_Q_TOTAL_CLIQUE_VARS (sum of the cliques' variable counts),
+ *   JT_Q_CPT_TOTAL (network trees: floats of the concatenated conditional
+ *     tables, 0 otherwise).
  * JT_Q_BYTES_LAST, JT_Q_LAST_SHARED and JT_Q_LAST_COLLECT_PASSES return
  * JT_E_STATE before the first propagation.  Other errors: JT_E_ARG. */
 #define JT_Q_N_SLOTS 0
@@ -287,6 +354,8 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_BYTES_LAST 19
 #define JT_Q_LAST_SHARED 20
 #define JT_Q_LAST_COLLECT_PASSES 21
+#define JT_Q_TOTAL_CLIQUE_VARS 22
+#define JT_Q_CPT_TOTAL 23
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and

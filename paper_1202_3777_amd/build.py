@@ -20,7 +20,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 HOST_SRCS = ["jt_plan.cpp", "jt_api.cpp"]
-DEVICE_SRCS = ["jt_kernels.hip", "jt_paper.hip", "jt_scratch.hip"]
+DEVICE_SRCS = ["jt_kernels.hip", "jt_paper.hip", "jt_bn.hip", "jt_scratch.hip"]
 DEVICE_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

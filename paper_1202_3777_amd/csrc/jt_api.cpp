@@ -23,6 +23,12 @@ hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s);
 hipError_t jt_launch_paper_slot(const JtDev &d, const JtPaperMsg *host_msgs, int n_msgs, const JtPaperBlk *dev_blocks,
                                 int n_blocks, const int32_t *dev_mu, int32_t layout, int32_t tpb, int32_t root,
                                 int slot, hipStream_t s);
+hipError_t jt_launch_bn_init(const JtDev &d, const JtFamily *fam, const int32_t *fam_rng, const JtCliqueShape *shape,
+                             int n_cliques, int64_t max_tiles, const float *cpts, hipStream_t s);
+hipError_t jt_launch_bn_counts(const JtDev &d, const JtFamily *fam, int n_fam, int64_t max_fsize, const int32_t *mu,
+                               const JtCliqueShape *shape, int n_active, float *counts, hipStream_t s);
+hipError_t jt_launch_bn_mstep(const JtFamily *fam, int n_fam, int64_t max_rows, const int32_t *card,
+                              const float *counts, float alpha, float *cpts, hipStream_t s);
 hipError_t jt_launch_read_out(const JtDev &d, int slot0, int n_slots, int64_t packed_total, float *dst,
                               double *log_z, hipStream_t s);
 
@@ -163,8 +169,16 @@ hipError_t upload_static(const jt::Plan &P, char *base, const float *init_potent
     // resets its counter, so no clearing is needed between propagations
     if (e == hipSuccess)
         e = hipMemsetAsync(base + P.off_icnt, 0, (size_t)P.n_regions * P.icnt_stride * sizeof(int32_t), s);
+    // network trees: family records, their ranges and the clique shapes (the
+    // initial tables are then computed from the conditional tables)
+    if (e == hipSuccess && !P.fam.empty()) {
+        e = up(P.off_fam, P.fam.data(), P.fam.size() * sizeof(JtFamily));
+        if (e == hipSuccess) e = up(P.off_fam_rng, P.fam_rng.data(), P.fam_rng.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = up(P.off_cshape, P.cshape.data(), P.cshape.size() * sizeof(JtCliqueShape));
+        if (e == hipSuccess) e = up(P.off_card, P.card.data(), P.card.size() * sizeof(int32_t));
+    }
     int64_t src_off = 0;
-    for (int32_t c = 0; c < P.n_cliques && e == hipSuccess; ++c) {
+    for (int32_t c = 0; c < P.n_cliques && e == hipSuccess && init_potentials; ++c) {
         const jt::CliqueInfo &C = P.cl[c];
         e = hipMemcpyAsync(base + P.off_init + C.init_off * sizeof(float), init_potentials + src_off,
                            (size_t)C.size * sizeof(float), hipMemcpyDefault, s);
@@ -430,16 +444,24 @@ extern "C" {
 
 const char *jt_last_error(void) { return g_err.c_str(); }
 
-jt_status jt_compile_index_maps(const jt_tree_desc *desc, jt_tree *out, size_t *device_bytes) {
+}  // extern "C"
+
+namespace {
+
+jt_status new_handle(const jt_tree_desc *desc, jt_tree *out, size_t *device_bytes, const jt::BnTree *bn) {
     try {
         if (!out || !device_bytes) return set_err(JT_E_ARG, "out or device_bytes is NULL");
         *out = nullptr;
         jt_tree t = new jt_tree_s();
         std::string err;
-        const jt_status rc = jt::compile_plan(desc, t->plan, err);
+        const jt_status rc = jt::compile_plan(desc, t->plan, err, bn ? &bn->families : nullptr, bn ? bn->cpt_total : 0);
         if (rc != JT_OK) {
             delete t;
             return set_err(rc, err);
+        }
+        if (bn) {
+            t->is_bn = true;
+            t->bn = *bn;
         }
         const jt::Plan &P = t->plan;
         t->ev_vars.assign(P.n_regions, {});
@@ -454,14 +476,66 @@ jt_status jt_compile_index_maps(const jt_tree_desc *desc, jt_tree *out, size_t *
     } catch (const std::bad_alloc &) {
         return set_err(JT_E_NO_MEM, "host allocation failed");
     } catch (...) {
-        return set_err(JT_E_ARG, "unexpected failure in jt_compile_index_maps");
+        return set_err(JT_E_ARG, "unexpected failure in compiling the tree");
     }
 }
 
-jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_potentials, void *hip_stream) {
+}  // namespace
+
+extern "C" {
+
+jt_status jt_compile_index_maps(const jt_tree_desc *desc, jt_tree *out, size_t *device_bytes) {
+    return new_handle(desc, out, device_bytes, nullptr);
+}
+
+jt_status jt_compile_bn(const jt_bn_desc *bn, jt_tree *out, size_t *device_bytes, int32_t *n_cliques) {
+    try {
+        if (!out || !device_bytes || !n_cliques) return set_err(JT_E_ARG, "NULL output");
+        *out = nullptr;
+        jt::BnTree T;
+        std::string err;
+        const jt_status rc = jt::compile_bn(bn, T, err);
+        if (rc != JT_OK) return set_err(rc, err);
+        const int32_t nc = (int32_t)T.cliques.size();
+        std::vector<int64_t> off(nc + 1, 0);
+        std::vector<int32_t> vars;
+        for (int32_t c = 0; c < nc; ++c) {
+            vars.insert(vars.end(), T.cliques[c].begin(), T.cliques[c].end());
+            off[c + 1] = (int64_t)vars.size();
+        }
+        jt_tree_desc d{bn->n_vars, T.card.data(), nc, off.data(), vars.data(), T.parent.data(), bn->n_slots, bn->tuning};
+        const jt_status rc2 = new_handle(&d, out, device_bytes, &T);
+        if (rc2 == JT_OK) *n_cliques = nc;
+        return rc2;
+    } catch (const std::bad_alloc &) {
+        return set_err(JT_E_NO_MEM, "host allocation failed");
+    }
+}
+
+jt_status jt_bn_structure(jt_tree t, int64_t *clique_off, int32_t *clique_vars, int32_t *parent,
+                          int32_t *family_clique) {
     if (jt_status rc = check_tree(t)) return rc;
+    if (!t->is_bn) return set_err(JT_E_STATE, "not a network tree");
+    if (!clique_off || !clique_vars || !parent || !family_clique) return set_err(JT_E_ARG, "NULL output");
+    const jt::BnTree &B = t->bn;
+    int64_t k = 0;
+    clique_off[0] = 0;
+    for (size_t c = 0; c < B.cliques.size(); ++c) {
+        for (int32_t v : B.cliques[c]) clique_vars[k++] = v;
+        clique_off[c + 1] = k;
+        parent[c] = B.parent[c];
+    }
+    for (const jt::FamilyReq &f : B.families) family_clique[f.var] = f.clique;
+    return JT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+jt_status bind_common(jt_tree t, void *workspace, size_t bytes, const float *init_potentials, void *hip_stream) {
     const jt::Plan &P = t->plan;
-    if (!workspace || !init_potentials) return set_err(JT_E_ARG, "workspace or init_potentials is NULL");
+    if (!workspace) return set_err(JT_E_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return set_err(JT_E_ARG, "workspace not 256-byte aligned");
     if (bytes < P.total_bytes)
         return set_err(JT_E_NO_MEM, "workspace of " + std::to_string(bytes) + " bytes, need " + std::to_string(P.total_bytes));
@@ -510,6 +584,89 @@ jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_po
     t->bound = true;
     t->propagated = false;
     g_err.clear();
+    return JT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_potentials, void *hip_stream) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!init_potentials) return set_err(JT_E_ARG, "init_potentials is NULL");
+    return bind_common(t, workspace, bytes, init_potentials, hip_stream);
+}
+
+jt_status jt_bind_bn(jt_tree t, void *workspace, size_t bytes, const float *cpts, void *hip_stream) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!t->is_bn) return set_err(JT_E_STATE, "not a network tree");
+    if (!cpts) return set_err(JT_E_ARG, "cpts is NULL");
+    if (jt_status rc = bind_common(t, workspace, bytes, nullptr, hip_stream)) return rc;
+    const jt::Plan &P = t->plan;
+    hipError_t e = hipSuccess;
+    try {
+        std::vector<int32_t> mu((size_t)std::max<int64_t>(1, P.fam_mu_total));
+        jt::family_mu_lists(P, mu.data());
+        e = hipMemcpyAsync(t->ws + P.off_fam_mu, mu.data(), (size_t)P.fam_mu_total * sizeof(int32_t),
+                           hipMemcpyHostToDevice, t->stream);
+        if (e == hipSuccess)
+            e = jt_launch_bn_init(t->dev, reinterpret_cast<const JtFamily *>(t->ws + P.off_fam),
+                                  reinterpret_cast<const int32_t *>(t->ws + P.off_fam_rng),
+                                  reinterpret_cast<const JtCliqueShape *>(t->ws + P.off_cshape), P.n_cliques,
+                                  P.max_tiles, cpts, t->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(t->stream);   // `mu` and `cpts` are read by now
+    } catch (const std::bad_alloc &) {
+        return set_err(JT_E_NO_MEM, "host allocation failed");
+    }
+    if (e != hipSuccess) {
+        t->bound = false;
+        return hip_err(e, "network initialization");
+    }
+    return JT_OK;
+}
+
+jt_status jt_bn_set_cpts(jt_tree t, const float *cpts) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!t->is_bn) return set_err(JT_E_STATE, "not a network tree");
+    if (!t->bound) return set_err(JT_E_STATE, "jt_bn_set_cpts before jt_bind_bn");
+    if (!cpts) return set_err(JT_E_ARG, "cpts is NULL");
+    const jt::Plan &P = t->plan;
+    hipError_t e = jt_launch_bn_init(t->dev, reinterpret_cast<const JtFamily *>(t->ws + P.off_fam),
+                                     reinterpret_cast<const int32_t *>(t->ws + P.off_fam_rng),
+                                     reinterpret_cast<const JtCliqueShape *>(t->ws + P.off_cshape), P.n_cliques,
+                                     P.max_tiles, cpts, t->stream);
+    if (e != hipSuccess) return hip_err(e, "network initialization");
+    t->propagated = false;
+    return JT_OK;
+}
+
+jt_status jt_bn_m_step(jt_tree t, const float *counts, float alpha, float *cpts) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!t->is_bn) return set_err(JT_E_STATE, "not a network tree");
+    if (!t->bound) return set_err(JT_E_STATE, "jt_bn_m_step before jt_bind_bn");
+    if (!counts || !cpts || !(alpha >= 0.f)) return set_err(JT_E_ARG, "NULL pointer or negative alpha");
+    const jt::Plan &P = t->plan;
+    int64_t rows = 1;
+    for (const JtFamily &F : P.fam) rows = std::max<int64_t>(rows, F.fsize / P.card[F.var]);
+    hipError_t e = jt_launch_bn_mstep(reinterpret_cast<const JtFamily *>(t->ws + P.off_fam), (int)P.fam.size(), rows,
+                                      reinterpret_cast<const int32_t *>(t->ws + P.off_card), counts, alpha, cpts,
+                                      t->stream);
+    if (e != hipSuccess) return hip_err(e, "M-step launch");
+    return JT_OK;
+}
+
+jt_status jt_bn_expected_counts(jt_tree t, int32_t n_active, float *counts) {
+    if (jt_status rc = check_tree(t)) return rc;
+    if (!t->is_bn) return set_err(JT_E_STATE, "not a network tree");
+    if (!counts) return set_err(JT_E_ARG, "counts is NULL");
+    if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
+    if (n_active < 1 || n_active > t->last_n_active) return set_err(JT_E_STATE, "slots not active in the last propagation");
+    const jt::Plan &P = t->plan;
+    hipError_t e = jt_launch_bn_counts(t->dev, reinterpret_cast<const JtFamily *>(t->ws + P.off_fam), (int)P.fam.size(),
+                                       P.max_fsize, reinterpret_cast<const int32_t *>(t->ws + P.off_fam_mu),
+                                       reinterpret_cast<const JtCliqueShape *>(t->ws + P.off_cshape), n_active, counts,
+                                       t->stream);
+    if (e != hipSuccess) return hip_err(e, "expected counts launch");
     return JT_OK;
 }
 
@@ -735,6 +892,13 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
         case JT_Q_SLOT_BYTES: *out = (int64_t)P.slot_bytes; break;
         case JT_Q_SHARED_BYTES: *out = (int64_t)P.total_bytes - (int64_t)P.slot_bytes * P.n_slots; break;
         case JT_Q_ROOT: *out = P.root; break;
+        case JT_Q_TOTAL_CLIQUE_VARS: {
+            int64_t k = 0;
+            for (const jt::CliqueInfo &C : P.cl) k += (int64_t)C.vars.size();
+            *out = k;
+            break;
+        }
+        case JT_Q_CPT_TOTAL: *out = P.cpt_total; break;
         case JT_Q_N_LANES: *out = P.n_lanes; break;
         case JT_Q_CLIQUE_LANE:
             if (arg < 0 || arg >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");

@@ -57,6 +57,9 @@ struct jt_tree_s {
     hipEvent_t fork_ev = nullptr;
     int last_mode = -1;
     int last_n_active = 0;
+    // Bayesian-network trees: the compiled network (cliques, families)
+    bool is_bn = false;
+    jt::BnTree bn;
     // paper-faithful schedule: its plan, its workspace (mapping lists,
     // message and block records), layout and threads per block
     jt::PaperPlan paper;

@@ -192,6 +192,24 @@ typedef struct {
     int64_t init_off, out_off;  // float offsets of its initial table and of its posterior in a slot
 } JtPaperBlk;
 
+// Bayesian-network front end: one job per variable v multiplies its
+// conditional table P(v | parents) into the clique that holds the family
+// (Algorithm 4's Initialization).  The family's entry index of clique entry
+// r = o*T + i is Jin[i] + Jout[o] (the family laid out as parents..., v).
+typedef struct {
+    int64_t jin_off, jout_off;  // int32 meta offsets
+    int64_t cpt_off;            // float offset of the table in the caller's concatenated tables
+    int64_t mu_off;             // int32 offset of the family's mapping lists (expected counts)
+    int32_t clique, fsize;      // clique holding the family; |P(v | parents)|
+    int32_t var, pad;
+} JtFamily;
+
+// Per-clique shape for the network front end's kernels.
+typedef struct {
+    int64_t init_off, n_tiles, size;
+    int32_t T, pad;
+} JtCliqueShape;
+
 // Everything a kernel needs, passed by value.
 typedef struct {
     const int32_t *meta;

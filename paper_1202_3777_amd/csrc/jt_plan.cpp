@@ -11,7 +11,9 @@
 #include <algorithm>
 #include <cstring>
 #include <limits>
+#include <functional>
 #include <map>
+#include <set>
 #include <stdexcept>
 
 namespace jt {
@@ -195,6 +197,43 @@ int32_t build_view(Plan &P, int32_t c, int32_t e) {
     for (int64_t cls = 0; cls < n_cls; ++cls) M.push_back(M[V.jin_off + M[V.perm_off + cls * V.m_in]]);
     P.views.push_back(V);
     return (int32_t)P.views.size() - 1;
+}
+
+// Jin / Jout tables of clique c seen through an arbitrary variable list
+// `vars` laid out row-major, last fastest (a conditional table's layout):
+// entry o*T + i of the clique has index Jin[i] + Jout[o] in that table.
+// Returns false when a variable of the list is not in the clique.
+bool build_projection(Plan &P, int32_t c, const std::vector<int32_t> &vars, int64_t &jin_off, int64_t &jout_off) {
+    const CliqueInfo &C = P.cl[c];
+    const size_t nd = C.digits.size();
+    std::vector<int64_t> ws(nd, 0);
+    int64_t stride = 1;
+    for (size_t q = vars.size(); q-- > 0;) {
+        bool found = false;
+        for (size_t k = 0; k < nd; ++k)
+            if (C.digits[k].var == vars[q]) {
+                ws[k] = stride * C.digits[k].w;
+                found = true;
+            }
+        if (!found) return false;
+        stride *= P.card[vars[q]];
+    }
+    std::vector<int32_t> &M = P.meta;
+    jin_off = (int64_t)M.size();
+    for (int64_t i = 0; i < C.T; ++i) {
+        int64_t j = 0;
+        for (size_t k = 0; k < nd; ++k)
+            if (!C.digits[k].outer) j += ((i / C.digits[k].stride) % C.digits[k].card) * ws[k];
+        M.push_back((int32_t)j);
+    }
+    jout_off = (int64_t)M.size();
+    for (int64_t o = 0; o < C.n_tiles; ++o) {
+        int64_t j = 0;
+        for (size_t k = 0; k < nd; ++k)
+            if (C.digits[k].outer) j += ((o / C.digits[k].ostride) % C.digits[k].card) * ws[k];
+        M.push_back((int32_t)j);
+    }
+    return true;
 }
 
 struct GatherSpec {
@@ -542,7 +581,8 @@ bool verify_plan(const Plan &P, std::string &why) {
 
 }  // namespace
 
-jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
+jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err, const std::vector<FamilyReq> *families,
+                       int64_t cpt_total) {
     if (!desc) return fail(err, JT_E_ARG, "desc is NULL");
     const int32_t nv = desc->n_vars, nc = desc->n_cliques;
     if (nv < 0) return fail(err, JT_E_ARG, "n_vars < 0");
@@ -793,6 +833,44 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
             P.edge[c].view_parent = build_view(P, P.parent[c], c);
         }
         P.cl[c].total_view = build_view(P, c, -1);
+        if ((int64_t)P.meta.size() > kMaxMeta) return fail(err, JT_E_TOO_LARGE, "index metadata too large");
+    }
+    // families of a Bayesian-network tree: their mapping into their cliques,
+    // sorted by clique (stable: ascending variable within a clique)
+    if (families) {
+        std::vector<FamilyReq> fr(*families);
+        std::stable_sort(fr.begin(), fr.end(), [](const FamilyReq &a, const FamilyReq &b) { return a.clique < b.clique; });
+        P.fam_rng.assign((size_t)nc + 1, 0);
+        for (const FamilyReq &f : fr) {
+            if (f.clique < 0 || f.clique >= nc) return fail(err, JT_E_ARG, "family clique out of range");
+            JtFamily F;
+            std::memset(&F, 0, sizeof(F));
+            if (!build_projection(P, f.clique, f.vars, F.jin_off, F.jout_off))
+                return fail(err, JT_E_ARG, "family of variable " + std::to_string(f.var) + " not in its clique");
+            int64_t fs = 1;
+            for (int32_t v : f.vars) fs *= P.card[v];
+            F.cpt_off = f.cpt_off;
+            F.mu_off = P.fam_mu_total;
+            F.clique = f.clique;
+            F.fsize = (int32_t)fs;
+            F.var = f.var;
+            P.fam_mu_total += P.cl[f.clique].size;
+            P.fam.push_back(F);
+            P.fam_rng[f.clique + 1]++;
+        }
+        for (int32_t c = 0; c < nc; ++c) P.fam_rng[c + 1] += P.fam_rng[c];
+        P.cpt_total = cpt_total;
+        for (int32_t c = 0; c < nc; ++c) {
+            JtCliqueShape sh;
+            sh.init_off = P.cl[c].init_off;
+            sh.n_tiles = P.cl[c].n_tiles;
+            sh.size = P.cl[c].size;
+            sh.T = P.cl[c].T;
+            sh.pad = 0;
+            P.cshape.push_back(sh);
+            P.max_tiles = std::max<int64_t>(P.max_tiles, sh.n_tiles);
+        }
+        for (const JtFamily &F : P.fam) P.max_fsize = std::max<int64_t>(P.max_fsize, F.fsize);
         if ((int64_t)P.meta.size() > kMaxMeta) return fail(err, JT_E_TOO_LARGE, "index metadata too large");
     }
     // clique c seen through edge e (c is one of its two ends)
@@ -1208,6 +1286,13 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err) {
     P.icnt_stride = align_up(std::max<int64_t>(1, (int64_t)P.items.size()), kAlignFloats);
     P.off_icnt = region(S * (size_t)P.icnt_stride * sizeof(int32_t));
     P.off_cltab = region(P.cltab.size() * sizeof(int64_t));
+    if (!P.fam.empty()) {
+        P.off_fam = region(P.fam.size() * sizeof(JtFamily));
+        P.off_fam_rng = region(P.fam_rng.size() * sizeof(int32_t));
+        P.off_fam_mu = region((size_t)P.fam_mu_total * sizeof(int32_t));
+        P.off_cshape = region(P.cshape.size() * sizeof(JtCliqueShape));
+        P.off_card = region(std::max<size_t>(1, P.card.size()) * sizeof(int32_t));
+    }
     P.total_bytes = off;
     P.slot_bytes = (size_t)P.coll_stride * sizeof(float) + (size_t)P.out_stride * sizeof(float) +
                    (size_t)P.sep_stride * sizeof(float) + (size_t)P.partial_stride * sizeof(float) +
@@ -1533,6 +1618,178 @@ void paper_mu_lists(const Plan &P, const PaperPlan &pp, int32_t layout, int32_t 
             }
         }
     }
+}
+
+void family_mu_lists(const Plan &P, int32_t *out) {
+    for (const JtFamily &F : P.fam) {
+        const CliqueInfo &C = P.cl[F.clique];
+        const int32_t *jin = P.meta.data() + F.jin_off;
+        const int32_t *jout = P.meta.data() + F.jout_off;
+        const int64_t m = C.size / F.fsize;
+        std::vector<int64_t> fill(F.fsize, 0);
+        for (int64_t o = 0; o < C.n_tiles; ++o)
+            for (int64_t i = 0; i < C.T; ++i) {
+                const int64_t j = jin[i] + jout[o];
+                out[F.mu_off + j * m + fill[j]++] = (int32_t)(o * C.T + i);
+            }
+    }
+}
+
+jt_status compile_bn(const jt_bn_desc *bn, BnTree &T, std::string &err) {
+    T = BnTree();
+    if (!bn || bn->n_vars < 1 || !bn->card || !bn->parent_off || (bn->parent_off[bn->n_vars] > 0 && !bn->parents))
+        return fail(err, JT_E_ARG, "bad network description");
+    const int32_t n = bn->n_vars;
+    T.card.assign(bn->card, bn->card + n);
+    std::vector<std::vector<int32_t>> pa(n);
+    if (bn->parent_off[0] != 0) return fail(err, JT_E_ARG, "parent_off[0] != 0");
+    for (int32_t v = 0; v < n; ++v) {
+        if (T.card[v] < 1) return fail(err, JT_E_ARG, "card < 1");
+        if (bn->parent_off[v + 1] < bn->parent_off[v] || bn->parent_off[v + 1] - bn->parent_off[v] > 63)
+            return fail(err, JT_E_ARG, "bad parent count");
+        for (int64_t k = bn->parent_off[v]; k < bn->parent_off[v + 1]; ++k) {
+            const int32_t p = bn->parents[k];
+            if (p < 0 || p >= n || p == v) return fail(err, JT_E_ARG, "parent out of range");
+            if (std::find(pa[v].begin(), pa[v].end(), p) != pa[v].end()) return fail(err, JT_E_ARG, "repeated parent");
+            pa[v].push_back(p);
+        }
+    }
+    // acyclic: Kahn's order over parent -> child
+    {
+        std::vector<int32_t> indeg(n, 0);
+        std::vector<std::vector<int32_t>> ch(n);
+        for (int32_t v = 0; v < n; ++v)
+            for (int32_t p : pa[v]) {
+                ch[p].push_back(v);
+                ++indeg[v];
+            }
+        std::vector<int32_t> q;
+        for (int32_t v = 0; v < n; ++v)
+            if (!indeg[v]) q.push_back(v);
+        for (size_t h = 0; h < q.size(); ++h)
+            for (int32_t c : ch[q[h]])
+                if (--indeg[c] == 0) q.push_back(c);
+        if ((int32_t)q.size() != n) return fail(err, JT_E_NOT_JUNCTION_TREE, "the parent links contain a cycle");
+    }
+    // moral graph (a bit matrix for adjacency tests, sets for neighbours)
+    std::vector<std::vector<char>> adj(n, std::vector<char>(n, 0));
+    std::vector<std::set<int32_t>> nbs(n);
+    auto link = [&](int32_t a, int32_t b) {
+        if (a != b && !adj[a][b]) {
+            adj[a][b] = adj[b][a] = 1;
+            nbs[a].insert(b);
+            nbs[b].insert(a);
+        }
+    };
+    for (int32_t v = 0; v < n; ++v) {
+        for (int32_t p : pa[v]) link(v, p);
+        for (size_t a = 0; a < pa[v].size(); ++a)
+            for (size_t b = a + 1; b < pa[v].size(); ++b) link(pa[v][a], pa[v][b]);
+    }
+    // greedy elimination, fewest fill-in edges, then fewest neighbours, then
+    // the lower id; each eliminated variable with its neighbours is a
+    // candidate clique
+    std::vector<char> gone(n, 0);
+    std::vector<std::vector<int32_t>> cand;
+    for (int32_t step = 0; step < n; ++step) {
+        int32_t best = -1;
+        int64_t bf = 0, bd = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (gone[v]) continue;
+            const std::vector<int32_t> nb(nbs[v].begin(), nbs[v].end());
+            int64_t fill = 0;
+            for (size_t a = 0; a < nb.size(); ++a)
+                for (size_t b = a + 1; b < nb.size(); ++b) fill += adj[nb[a]][nb[b]] ? 0 : 1;
+            if (best < 0 || fill < bf || (fill == bf && (int64_t)nb.size() < bd)) {
+                best = v;
+                bf = fill;
+                bd = (int64_t)nb.size();
+            }
+        }
+        std::vector<int32_t> cl{best};
+        for (int32_t u : nbs[best]) cl.push_back(u);
+        for (size_t a = 1; a < cl.size(); ++a)
+            for (size_t b = a + 1; b < cl.size(); ++b) link(cl[a], cl[b]);
+        gone[best] = 1;
+        for (int32_t u : nbs[best]) nbs[u].erase(best);
+        nbs[best].clear();
+        std::sort(cl.begin(), cl.end());
+        int64_t size = 1;
+        for (int32_t v : cl) {
+            size *= T.card[v];
+            if (size > std::numeric_limits<int32_t>::max())
+                return fail(err, JT_E_TOO_LARGE, "a clique of the triangulated network has 2^31 or more entries");
+        }
+        cand.push_back(cl);
+    }
+    // maximal candidates, in elimination order
+    for (size_t a = 0; a < cand.size(); ++a) {
+        bool sub = false;
+        for (size_t b = 0; b < cand.size() && !sub; ++b) {
+            if (a == b) continue;
+            const bool incl = std::includes(cand[b].begin(), cand[b].end(), cand[a].begin(), cand[a].end());
+            // equal sets: keep the first
+            if (incl && (cand[b].size() > cand[a].size() || b < a)) sub = true;
+        }
+        if (!sub) T.cliques.push_back(cand[a]);
+    }
+    const int32_t nc = (int32_t)T.cliques.size();
+    // maximum-weight spanning tree over separator sizes (Kruskal)
+    struct E { int32_t w, a, b; };
+    std::vector<E> es;
+    for (int32_t a = 0; a < nc; ++a)
+        for (int32_t b = a + 1; b < nc; ++b) {
+            std::vector<int32_t> x;
+            std::set_intersection(T.cliques[a].begin(), T.cliques[a].end(), T.cliques[b].begin(), T.cliques[b].end(),
+                                  std::back_inserter(x));
+            es.push_back({(int32_t)x.size(), a, b});
+        }
+    std::stable_sort(es.begin(), es.end(), [](const E &x, const E &y) { return x.w > y.w; });
+    std::vector<int32_t> uf(nc);
+    for (int32_t c = 0; c < nc; ++c) uf[c] = c;
+    std::function<int32_t(int32_t)> root = [&](int32_t x) { return uf[x] == x ? x : (uf[x] = root(uf[x])); };
+    std::vector<std::vector<int32_t>> nbr(nc);
+    for (const E &e : es) {
+        const int32_t ra = root(e.a), rb = root(e.b);
+        if (ra == rb) continue;
+        uf[ra] = rb;
+        nbr[e.a].push_back(e.b);
+        nbr[e.b].push_back(e.a);
+    }
+    T.parent.assign(nc, -1);
+    {
+        std::vector<char> seen(nc, 0);
+        std::vector<int32_t> q{0};
+        seen[0] = 1;
+        for (size_t h = 0; h < q.size(); ++h) {
+            std::vector<int32_t> nb = nbr[q[h]];
+            std::sort(nb.begin(), nb.end());
+            for (int32_t y : nb)
+                if (!seen[y]) {
+                    seen[y] = 1;
+                    T.parent[y] = q[h];
+                    q.push_back(y);
+                }
+        }
+    }
+    // families
+    int64_t off = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        std::vector<int32_t> fam(pa[v]);
+        fam.push_back(v);
+        std::vector<int32_t> fs(fam);
+        std::sort(fs.begin(), fs.end());
+        int32_t home = -1;
+        for (int32_t c = 0; c < nc && home < 0; ++c)
+            if (std::includes(T.cliques[c].begin(), T.cliques[c].end(), fs.begin(), fs.end())) home = c;
+        if (home < 0) return fail(err, JT_E_ARG, "internal: a family is in no clique");
+        int64_t size = 1;
+        for (int32_t u : fam) size *= T.card[u];
+        T.families.push_back({home, v, fam, off});
+        off += size;
+    }
+    T.cpt_total = off;
+    return JT_OK;
 }
 
 void evidence_tables(const Plan &P, const std::vector<int32_t> &vars, const std::vector<int32_t> &states,

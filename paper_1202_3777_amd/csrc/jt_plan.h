@@ -63,6 +63,15 @@ struct Launch {
     int32_t chunk_cap = 0;
 };
 
+// A family (variable and parents) to be mapped into a clique: the index of
+// clique entry r in the family's table laid out as vars (last fastest).
+struct FamilyReq {
+    int32_t clique;
+    int32_t var;
+    std::vector<int32_t> vars;   // parents..., var
+    int64_t cpt_off;             // in the concatenated conditional tables
+};
+
 struct Plan {
     // shape choices (defaults filled in)
     jt_tuning tune{};
@@ -124,6 +133,14 @@ struct Plan {
     // count change (evidence tables, collect sources, work lists): one range
     size_t off_dyn = 0, dyn_bytes = 0;
     std::vector<int64_t> cltab;      // per clique: posterior offset, size, packed offset
+    // Bayesian-network trees: the families, sorted by clique, and each
+    // clique's range of them; the mapping lists of each family
+    std::vector<JtFamily> fam;
+    std::vector<int32_t> fam_rng;    // [n_cliques + 1]
+    int64_t fam_mu_total = 0, cpt_total = 0;
+    std::vector<JtCliqueShape> cshape;   // per clique (network trees)
+    int64_t max_tiles = 0, max_fsize = 0;
+    size_t off_fam = 0, off_fam_rng = 0, off_fam_mu = 0, off_cshape = 0, off_card = 0;
     size_t slot_bytes = 0;           // workspace bytes that scale with the slot count (per slot)
 
     // statistics
@@ -147,7 +164,28 @@ void build_paper_plan(const Plan &plan, PaperPlan &pp);
 void paper_mu_lists(const Plan &plan, const PaperPlan &pp, int32_t layout, int32_t *out);
 
 // Build the plan; returns JT_OK or an error code with `err` filled in.
-jt_status compile_plan(const jt_tree_desc *desc, Plan &plan, std::string &err);
+// `families` (Bayesian-network trees only): the conditional tables to map
+// into their cliques; cpt_total their concatenated size.
+jt_status compile_plan(const jt_tree_desc *desc, Plan &plan, std::string &err,
+                       const std::vector<FamilyReq> *families = nullptr, int64_t cpt_total = 0);
+
+// The family mapping lists of a Bayesian-network tree (list j of family k:
+// the entries of its clique whose family index is j, ascending), at each
+// family's mu_off: fam_mu_total int32.
+void family_mu_lists(const Plan &plan, int32_t *out);
+
+// Bayesian network -> junction tree (host): moralize, triangulate by greedy
+// min-fill elimination, keep the maximal cliques (variables ascending), join
+// them by a maximum-weight spanning tree over separator sizes, root at
+// clique 0, and give every family the lowest-id clique that holds it.
+struct BnTree {
+    std::vector<int32_t> card;
+    std::vector<std::vector<int32_t>> cliques;
+    std::vector<int32_t> parent;
+    std::vector<FamilyReq> families;
+    int64_t cpt_total = 0;
+};
+jt_status compile_bn(const jt_bn_desc *bn, BnTree &out, std::string &err);
 
 // Per-propagation schedule of a batched tree: which (clique, slot) pairs the
 // collect sweep computes and where every slot reads collect data from.

@@ -341,3 +341,73 @@ def make_separator_sweep(sep_vars: int, seed: int = 0, n_cliques: int = 40, fres
     off, flat = _pack(cvars)
     return Instance(name=f"sepsweep{sep_vars}", seed=seed, card=card_a, clique_off=off, clique_vars=flat,
                     parent=parent, potentials=pot, table_off=table_off, evidence=ev)
+
+
+# ----------------------------------------------------------------------------
+# Bayesian networks (the front end's input): a random DAG, conditional
+# tables, and evidence sets drawn from the network.
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class BayesNet:
+    card: np.ndarray          # int32 [n_vars]
+    parent_off: np.ndarray    # int64 [n_vars + 1]
+    parents: np.ndarray       # int32 [parent_off[-1]]; table layout (parents..., v)
+    cpts: np.ndarray          # float32, the conditional tables concatenated in variable order
+    cpt_off: np.ndarray       # int64 [n_vars + 1]
+
+    @property
+    def n_vars(self) -> int:
+        return int(self.card.shape[0])
+
+    def parents_of(self, v: int) -> np.ndarray:
+        return self.parents[self.parent_off[v]:self.parent_off[v + 1]]
+
+    def cpt(self, v: int) -> np.ndarray:
+        """P(v | parents) shaped (card of each parent..., card[v])."""
+        shape = [int(self.card[p]) for p in self.parents_of(v)] + [int(self.card[v])]
+        return self.cpts[self.cpt_off[v]:self.cpt_off[v + 1]].reshape(shape)
+
+
+def make_bn(seed: int = 0, n_vars: int = 16, max_parents: int = 3, cards=(2, 3), window: Optional[int] = None) -> BayesNet:
+    """Variable v picks 0..max_parents parents uniformly among the earlier
+    variables (within the last `window` of them when given, which keeps the
+    triangulated cliques small on long networks); each row of P(v | parents)
+    is a Dirichlet(1) draw."""
+    rng = _rng(seed)
+    card = np.asarray([int(rng.choice(cards)) for _ in range(n_vars)], dtype=np.int32)
+    pa: List[List[int]] = []
+    for v in range(n_vars):
+        lo = 0 if window is None else max(0, v - window)
+        pool = list(range(lo, v))
+        k = int(rng.integers(0, min(max_parents, len(pool)) + 1)) if pool else 0
+        pa.append([int(x) for x in rng.choice(pool, size=k, replace=False)] if k else [])
+    parent_off = np.zeros(n_vars + 1, dtype=np.int64)
+    for v in range(n_vars):
+        parent_off[v + 1] = parent_off[v] + len(pa[v])
+    parents = np.asarray([p for ps in pa for p in ps], dtype=np.int32)
+    cpt_off = np.zeros(n_vars + 1, dtype=np.int64)
+    tabs = []
+    for v in range(n_vars):
+        rows = int(np.prod([int(card[p]) for p in pa[v]], dtype=np.int64)) if pa[v] else 1
+        t = rng.dirichlet(np.ones(int(card[v])), size=rows).reshape(-1)
+        tabs.append(t.astype(np.float32))
+        cpt_off[v + 1] = cpt_off[v] + t.shape[0]
+    return BayesNet(card=card, parent_off=parent_off, parents=parents, cpts=np.concatenate(tabs), cpt_off=cpt_off)
+
+
+def sample_bn_evidence(bn: BayesNet, n_sets: int, n_obs: Tuple[int, int], seed: int = 0):
+    """Evidence sets drawn from the network: one ancestral sample per set
+    (variables in index order, every parent precedes its child), of which a
+    uniformly chosen subset of n_obs variables is observed."""
+    rng = _rng(seed)
+    out = []
+    for _ in range(n_sets):
+        x = np.zeros(bn.n_vars, dtype=np.int64)
+        for v in range(bn.n_vars):
+            row = bn.cpt(v)[tuple(int(x[p]) for p in bn.parents_of(v))].astype(np.float64)
+            x[v] = int(rng.choice(int(bn.card[v]), p=row / row.sum()))
+        k = int(rng.integers(n_obs[0], n_obs[1] + 1))
+        vs = np.sort(rng.choice(bn.n_vars, size=min(k, bn.n_vars), replace=False)).astype(np.int32)
+        out.append((vs, x[vs].astype(np.int32)))
+    return out

@@ -59,10 +59,13 @@ JT_Q_FUSED_LAUNCH_LANE = 18
 JT_Q_BYTES_LAST = 19
 JT_Q_LAST_SHARED = 20
 JT_Q_LAST_COLLECT_PASSES = 21
+JT_Q_TOTAL_CLIQUE_VARS = 22
+JT_Q_CPT_TOTAL = 23
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_read_out", "jt_paper_bytes", "jt_paper_bind", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
-            "jt_propagate_scratch", "jt_free", "jt_last_error"]
+            "jt_propagate_scratch", "jt_compile_bn", "jt_bn_structure", "jt_bind_bn", "jt_bn_expected_counts",
+            "jt_bn_m_step", "jt_bn_set_cpts", "jt_free", "jt_last_error"]
 
 
 class JTError(RuntimeError):
@@ -77,6 +80,12 @@ class jt_tuning(ctypes.Structure):
 
 
 TUNING_FIELDS = [f for f, _ in jt_tuning._fields_]
+
+
+class jt_bn_desc(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("card", ctypes.POINTER(ctypes.c_int32)),
+                ("parent_off", ctypes.POINTER(ctypes.c_int64)), ("parents", ctypes.POINTER(ctypes.c_int32)),
+                ("n_slots", ctypes.c_int32), ("tuning", ctypes.POINTER(jt_tuning))]
 
 
 class jt_tree_desc(ctypes.Structure):
@@ -116,9 +125,16 @@ def load():
     lib.jt_read_out.argtypes = [V, I32, I32, V, V]
     lib.jt_paper_bytes.argtypes = [V, ctypes.POINTER(SZ)]
     lib.jt_paper_bind.argtypes = [V, V, SZ, I32, I32]
+    lib.jt_compile_bn.argtypes = [ctypes.POINTER(jt_bn_desc), ctypes.POINTER(V), ctypes.POINTER(SZ), P32]
+    lib.jt_bn_structure.argtypes = [V, P64, P32, P32, P32]
+    lib.jt_bind_bn.argtypes = [V, V, SZ, V, V]
+    lib.jt_bn_expected_counts.argtypes = [V, I32, V]
+    lib.jt_bn_m_step.argtypes = [V, V, ctypes.c_float, V]
+    lib.jt_bn_set_cpts.argtypes = [V, V]
     for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
               "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
-              "jt_propagate_scratch", "jt_read_out", "jt_paper_bytes", "jt_paper_bind"):
+              "jt_propagate_scratch", "jt_read_out", "jt_paper_bytes", "jt_paper_bind", "jt_compile_bn",
+              "jt_bn_structure", "jt_bind_bn", "jt_bn_expected_counts", "jt_bn_m_step", "jt_bn_set_cpts"):
         getattr(lib, f).restype = I32
     lib.jt_free.argtypes = [V]
     lib.jt_free.restype = None
@@ -201,6 +217,62 @@ def jt_marginals_all(h, slot: int, out_ptr: Optional[int]) -> float:
 def jt_read_out(h, slot0: int, n: int, posteriors_ptr: int, log_z_ptr: int):
     _check(load().jt_read_out(h, int(slot0), int(n), ctypes.c_void_p(posteriors_ptr), ctypes.c_void_p(log_z_ptr)),
            "jt_read_out")
+
+
+def _tuning_ptr(tuning):
+    if not tuning:
+        return None
+    unknown = set(tuning) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    return ctypes.pointer(jt_tuning(*[int(tuning.get(f, 0)) for f in TUNING_FIELDS]))
+
+
+def jt_compile_bn(card, parent_off, parents, n_slots: int = 1, tuning: Optional[dict] = None):
+    """Returns (handle, device_bytes, n_cliques)."""
+    lib = load()
+    card = np.ascontiguousarray(card, dtype=np.int32)
+    off = np.ascontiguousarray(parent_off, dtype=np.int64)
+    pa = np.ascontiguousarray(parents, dtype=np.int32)
+    pa_p = _p(pa, ctypes.c_int32) if pa.shape[0] else ctypes.POINTER(ctypes.c_int32)()
+    d = jt_bn_desc(int(card.shape[0]), _p(card, ctypes.c_int32), _p(off, ctypes.c_int64), pa_p, int(n_slots),
+                   _tuning_ptr(tuning))
+    h = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    ncl = ctypes.c_int32()
+    _check(lib.jt_compile_bn(ctypes.byref(d), ctypes.byref(h), ctypes.byref(nbytes), ctypes.byref(ncl)),
+           "jt_compile_bn")
+    return h, int(nbytes.value), int(ncl.value)
+
+
+def jt_bn_structure(h, n_vars: int, n_cliques: int):
+    """(clique_off, clique_vars, parent, family_clique) of a network tree."""
+    nvars = jt_query(h, JT_Q_TOTAL_CLIQUE_VARS)
+    off = np.empty(n_cliques + 1, dtype=np.int64)
+    cv = np.empty(max(1, nvars), dtype=np.int32)
+    par = np.empty(n_cliques, dtype=np.int32)
+    fam = np.empty(n_vars, dtype=np.int32)
+    _check(load().jt_bn_structure(h, _p(off, ctypes.c_int64), _p(cv, ctypes.c_int32), _p(par, ctypes.c_int32),
+                                  _p(fam, ctypes.c_int32)), "jt_bn_structure")
+    return off, cv[:nvars], par, fam
+
+
+def jt_bind_bn(h, workspace_ptr: int, nbytes: int, cpts_ptr: int, stream_ptr: int):
+    _check(load().jt_bind_bn(h, ctypes.c_void_p(workspace_ptr), nbytes, ctypes.c_void_p(cpts_ptr),
+                             ctypes.c_void_p(stream_ptr)), "jt_bind_bn")
+
+
+def jt_bn_expected_counts(h, n_active: int, counts_ptr: int):
+    _check(load().jt_bn_expected_counts(h, int(n_active), ctypes.c_void_p(counts_ptr)), "jt_bn_expected_counts")
+
+
+def jt_bn_m_step(h, counts_ptr: int, alpha: float, cpts_ptr: int):
+    _check(load().jt_bn_m_step(h, ctypes.c_void_p(counts_ptr), float(alpha), ctypes.c_void_p(cpts_ptr)),
+           "jt_bn_m_step")
+
+
+def jt_bn_set_cpts(h, cpts_ptr: int):
+    _check(load().jt_bn_set_cpts(h, ctypes.c_void_p(cpts_ptr)), "jt_bn_set_cpts")
 
 
 def jt_paper_bytes(h) -> int:
@@ -372,3 +444,60 @@ class JunctionTree(JunctionTreePlan):
         out = self.torch.empty(int(self.table_off[-1]), dtype=self.torch.float32, device=self.device)
         lz = jt_marginals_all(self.handle, slot, out.data_ptr())
         return out, lz
+
+
+class BayesNetTree(JunctionTree):
+    """A Bayesian network compiled into a junction tree (jt_compile_bn) and
+    bound with its conditional tables multiplied into the cliques on the
+    device (jt_bind_bn); evidence, propagation and read-out as for any tree,
+    plus the EM steps (expected counts, M-step, new tables)."""
+
+    def __init__(self, bn, n_slots: int = 1, device: str = "cuda", stream=None, tuning: Optional[dict] = None):
+        import torch
+        self.tuning = dict(tuning) if tuning else {}
+        self.bn = bn
+        self.n_slots = int(n_slots)
+        self.handle, self.device_bytes, self.n_cliques = jt_compile_bn(bn.card, bn.parent_off, bn.parents, n_slots,
+                                                                       self.tuning)
+        self.clique_off, self.clique_vars, self.parent, self.family_clique = jt_bn_structure(
+            self.handle, bn.n_vars, self.n_cliques)
+        self.card = np.ascontiguousarray(bn.card, dtype=np.int32)
+        self.table_size = np.asarray([jt_query(self.handle, JT_Q_TABLE_SIZE, c) for c in range(self.n_cliques)],
+                                     dtype=np.int64)
+        self.table_off = np.concatenate([[0], np.cumsum(self.table_size)]).astype(np.int64)
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(self.device_bytes, dtype=torch.uint8, device=self.device)
+            self.cpts = torch.from_numpy(np.ascontiguousarray(bn.cpts, dtype=np.float32)).to(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        jt_bind_bn(self.handle, self.workspace.data_ptr(), self.device_bytes, self.cpts.data_ptr(),
+                   self.stream.cuda_stream)
+
+    def clique_vars_of(self, c: int) -> np.ndarray:
+        return self.clique_vars[self.clique_off[c]:self.clique_off[c + 1]]
+
+    def expected_counts(self, n_active: Optional[int] = None):
+        """Device tensor of sum over slots of P(family | e_slot), laid out like the tables."""
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty(int(jt_query(self.handle, JT_Q_CPT_TOTAL)), dtype=self.torch.float32,
+                                   device=self.device)
+        jt_bn_expected_counts(self.handle, n_active or self.n_slots, out.data_ptr())
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)   # later torch work sees the result
+        return out
+
+    def m_step(self, counts, alpha: float = 0.0):
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty_like(counts)
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        jt_bn_m_step(self.handle, counts.data_ptr(), alpha, out.data_ptr())
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def set_cpts(self, cpts):
+        """New conditional tables (device tensor): the clique tables are
+        recomputed on the device before the next propagation."""
+        self.cpts = cpts
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        jt_bn_set_cpts(self.handle, cpts.data_ptr())
