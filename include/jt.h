@@ -273,6 +273,25 @@ jt_status jt_bn_expected_counts(jt_tree t, int32_t n_active, float *counts);
 jt_status jt_bn_m_step(jt_tree t, const float *counts, float alpha, float *cpts);
 jt_status jt_bn_set_cpts(jt_tree t, const float *cpts);
 
+/* Merging small separators (the paper's Sec. 5 future work: fewer, larger
+ * messages for trees of many small cliques).  jt_compile_merged validates
+ * the caller's tree and contracts, bottom-up from its root (children before
+ * parents, ascending ids), every edge whose separator has at most max_sep
+ * entries while the merged clique's table stays within max_entries entries;
+ * a merged clique lists the union of its cliques' variables ascending.  The
+ * handle keeps the caller's cliques as its interface: jt_bind takes their
+ * tables (concatenated in their order) and the device multiplies them into
+ * the merged cliques; jt_marginal / jt_marginals_all return the caller's
+ * cliques' posteriors, marginalized from their merged cliques on the device
+ * (FP64 sums; they synchronize the stream); evidence, propagation and the
+ * schedules are unchanged.  Exact results equal those of the unmerged tree
+ * (within the stated tolerance).  *n_compiled receives the merged clique
+ * count; jt_read_out, the mapping queries and the paper schedule refer to the
+ * merged cliques.  Errors: as jt_compile_index_maps, and JT_E_ARG for bounds
+ * below 1. */
+jt_status jt_compile_merged(const jt_tree_desc *desc, int32_t max_sep, int64_t max_entries, jt_tree *out,
+                            size_t *device_bytes, int32_t *n_compiled);
+
 /* Asynchronous read-out on the bound stream: the posteriors of slots
  * [slot0, slot0 + n) packed in clique order, slot after slot
  * (n * sum |phi_X| floats), and their log Z_e (n doubles, -inf where the
@@ -329,7 +348,10 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *     evidence-free slot included),
  *   JT_Q_TOTAL_CLIQUE_VARS (sum of the cliques' variable counts),
  *   JT_Q_CPT_TOTAL (network trees: floats of the concatenated conditional
- *     tables, 0 otherwise).
+ *     tables, 0 otherwise),
+ *   JT_Q_N_COMPILED_CLIQUES, JT_Q_COMPILED_TABLE_SIZE (arg = clique): the
+ *     cliques the schedules run on (for a merged tree its merged cliques;
+ *     JT_Q_TABLE_SIZE and JT_Q_TOTAL_ENTRIES describe the caller's).
  * JT_Q_BYTES_LAST, JT_Q_LAST_SHARED and JT_Q_LAST_COLLECT_PASSES return
  * JT_E_STATE before the first propagation.  Other errors: JT_E_ARG. */
 #define JT_Q_N_SLOTS 0
@@ -356,6 +378,8 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_LAST_COLLECT_PASSES 21
 #define JT_Q_TOTAL_CLIQUE_VARS 22
 #define JT_Q_CPT_TOTAL 23
+#define JT_Q_N_COMPILED_CLIQUES 24
+#define JT_Q_COMPILED_TABLE_SIZE 25
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and

@@ -18,7 +18,10 @@ Runs on one GPU and prints one JSON object (also written to --out):
     from a captured graph (the difference is the launch cost the graph
     removes), for the paper's schedule and the tiled one; the kernels' own
     busy time comes from a rocprofv3 kernel trace of the same command;
-  * margin      -- the tiled engine's speedup over the paper's kernels.
+  * margin      -- the tiled engine's speedup over the paper's kernels;
+  * merge       -- the paper's future work (Sec. 5): the same trees with
+    their small separators merged away, time per propagation against the
+    unmerged tree (the caller's clique posteriors read out in both).
 
 Every timed propagation is checked against the oracle first.
 """
@@ -60,7 +63,9 @@ def main():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=None)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--sections", default="block_size,sep_sweep,overhead,merge")
     args = ap.parse_args()
+    sections = set(args.sections.split(","))
     import torch
 
     import oracle
@@ -75,7 +80,7 @@ def main():
         return t
 
     # Fig. 5 and Fig. 8
-    trees = {"large separators (12 cliques of the large-clique tree)": make_instance("c2", 0, n_cliques=12),
+    trees = {} if "block_size" not in sections else {"large separators (12 cliques of the large-clique tree)": make_instance("c2", 0, n_cliques=12),
              "small separators (the batched tree, one evidence set)": make_instance("c4", 0, n_slots=1)}
     tpbs = [16, 32, 64, 128, 256, 512] if not args.quick else [32, 256]
     out["block_size"], out["layout"] = {}, {}
@@ -100,7 +105,7 @@ def main():
 
     # Fig. 6: speedup against the average separator size
     out["sep_sweep"] = []
-    for s in (range(1, 13) if not args.quick else (2, 6, 10)):
+    for s in (range(1, 13) if not args.quick else (2, 6, 10)) if "sep_sweep" in sections else ():
         inst = make_separator_sweep(s, seed=s)
         plan = oracle.Plan.from_instance(inst)
         t0 = time.perf_counter()
@@ -127,7 +132,7 @@ def main():
     # Fig. 7: launch-by-launch against graph replay
     out["overhead"] = {}
     for name, inst in (("small separators", make_instance("c4", 0, n_slots=1)),
-                       ("large separators", make_instance("c2", 0, n_cliques=12))):
+                       ("large separators", make_instance("c2", 0, n_cliques=12))) if "overhead" in sections else ():
         t = tree_of(inst)
         t.paper_bind("interleaved", 64)
         row = {"paper_eager_ms": _time(torch, t, "paper", reps), "paper_graph_ms": _time(torch, t, "paper_graph", reps),
@@ -139,6 +144,29 @@ def main():
         out.setdefault("margin", {})[name] = row["paper_graph_ms"] / row["tiled_graph_ms"]
         print(name, json.dumps(row), flush=True)
         del t
+    # Sec. 5: merging small separators
+    out["merge"] = {}
+    if "merge" in sections:
+        cases = [("tiny binary tree (20 cliques of 32 entries)", make_instance("c1", 0), [(4, 1024), (4, 1 << 14)]),
+                 ("batched tree's shape, one evidence set", make_instance("c4", 0, n_slots=1),
+                  [(8, 1 << 17), (16, 1 << 18)])]
+        for name, inst, bounds in cases:
+            plan = oracle.Plan.from_instance(inst)
+            res = plan.run(inst.potentials, *inst.evidence[0])
+            t = jt.JunctionTree.from_instance(inst, n_slots=1)
+            row = {"unmerged": {"cliques": inst.n_cliques, "launches": t.query(jt.JT_Q_N_LAUNCHES_FUSED),
+                                "ms": _time(torch, t, "graph", max(reps, 20))}}
+            _check(t, inst, plan, res)
+            del t
+            for ms_, me in bounds:
+                t = jt.JunctionTree.from_instance(inst, n_slots=1, merge=(ms_, me))
+                row[f"max_sep {ms_}, max_entries {me}"] = {
+                    "cliques": t.n_compiled, "launches": t.query(jt.JT_Q_N_LAUNCHES_FUSED),
+                    "ms": _time(torch, t, "graph", max(reps, 20))}
+                _check(t, inst, plan, res)
+                del t
+            out["merge"][name] = row
+            print(name, json.dumps(row), flush=True)
     s = json.dumps(out)
     print(s, flush=True)
     if args.out:

@@ -25,8 +25,9 @@ hipError_t jt_launch_paper_slot(const JtDev &d, const JtPaperMsg *host_msgs, int
                                 int slot, hipStream_t s);
 hipError_t jt_launch_bn_init(const JtDev &d, const JtFamily *fam, const int32_t *fam_rng, const JtCliqueShape *shape,
                              int n_cliques, int64_t max_tiles, const float *cpts, hipStream_t s);
-hipError_t jt_launch_bn_counts(const JtDev &d, const JtFamily *fam, int n_fam, int64_t max_fsize, const int32_t *mu,
-                               const JtCliqueShape *shape, int n_active, float *counts, hipStream_t s);
+hipError_t jt_launch_family_marginal(const JtDev &d, const JtFamily *fam, int fam0, int n_fam, int64_t max_fsize,
+                                     const int32_t *mu, const JtCliqueShape *shape, int s0, int n_slots, float *dst,
+                                     int64_t dst_base, hipStream_t s);
 hipError_t jt_launch_bn_mstep(const JtFamily *fam, int n_fam, int64_t max_rows, const int32_t *card,
                               const float *counts, float alpha, float *cpts, hipStream_t s);
 hipError_t jt_launch_read_out(const JtDev &d, int slot0, int n_slots, int64_t packed_total, float *dst,
@@ -448,13 +449,16 @@ const char *jt_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
-jt_status new_handle(const jt_tree_desc *desc, jt_tree *out, size_t *device_bytes, const jt::BnTree *bn) {
+jt_status new_handle(const jt_tree_desc *desc, jt_tree *out, size_t *device_bytes, const jt::BnTree *bn,
+                     const jt::MergedTree *merged = nullptr) {
     try {
         if (!out || !device_bytes) return set_err(JT_E_ARG, "out or device_bytes is NULL");
         *out = nullptr;
         jt_tree t = new jt_tree_s();
         std::string err;
-        const jt_status rc = jt::compile_plan(desc, t->plan, err, bn ? &bn->families : nullptr, bn ? bn->cpt_total : 0);
+        const std::vector<jt::FamilyReq> *fam = bn ? &bn->families : merged ? &merged->families : nullptr;
+        const int64_t ftot = bn ? bn->cpt_total : merged ? merged->total : 0;
+        const jt_status rc = jt::compile_plan(desc, t->plan, err, fam, ftot);
         if (rc != JT_OK) {
             delete t;
             return set_err(rc, err);
@@ -462,6 +466,10 @@ jt_status new_handle(const jt_tree_desc *desc, jt_tree *out, size_t *device_byte
         if (bn) {
             t->is_bn = true;
             t->bn = *bn;
+        }
+        if (merged) {
+            t->is_merged = true;
+            t->merged = *merged;
         }
         const jt::Plan &P = t->plan;
         t->ev_vars.assign(P.n_regions, {});
@@ -506,6 +514,32 @@ jt_status jt_compile_bn(const jt_bn_desc *bn, jt_tree *out, size_t *device_bytes
         jt_tree_desc d{bn->n_vars, T.card.data(), nc, off.data(), vars.data(), T.parent.data(), bn->n_slots, bn->tuning};
         const jt_status rc2 = new_handle(&d, out, device_bytes, &T);
         if (rc2 == JT_OK) *n_cliques = nc;
+        return rc2;
+    } catch (const std::bad_alloc &) {
+        return set_err(JT_E_NO_MEM, "host allocation failed");
+    }
+}
+
+jt_status jt_compile_merged(const jt_tree_desc *desc, int32_t max_sep, int64_t max_entries, jt_tree *out,
+                            size_t *device_bytes, int32_t *n_compiled) {
+    try {
+        if (!desc || !out || !device_bytes || !n_compiled) return set_err(JT_E_ARG, "NULL argument");
+        *out = nullptr;
+        jt::MergedTree M;
+        std::string err;
+        const jt_status rc = jt::merge_tree(desc, max_sep, max_entries, M, err);
+        if (rc != JT_OK) return set_err(rc, err);
+        const int32_t nm = (int32_t)M.cliques.size();
+        std::vector<int64_t> off(nm + 1, 0);
+        std::vector<int32_t> vars;
+        for (int32_t c = 0; c < nm; ++c) {
+            vars.insert(vars.end(), M.cliques[c].begin(), M.cliques[c].end());
+            off[c + 1] = (int64_t)vars.size();
+        }
+        jt_tree_desc d{desc->n_vars, M.card.data(), nm, off.data(), vars.data(), M.parent.data(), desc->n_slots,
+                       desc->tuning};
+        const jt_status rc2 = new_handle(&d, out, device_bytes, nullptr, &M);
+        if (rc2 == JT_OK) *n_compiled = nm;
         return rc2;
     } catch (const std::bad_alloc &) {
         return set_err(JT_E_NO_MEM, "host allocation failed");
@@ -591,9 +625,14 @@ jt_status bind_common(jt_tree t, void *workspace, size_t bytes, const float *ini
 
 extern "C" {
 
+jt_status bind_families(jt_tree t, void *workspace, size_t bytes, const float *cpts, void *hip_stream);
+
 jt_status jt_bind(jt_tree t, void *workspace, size_t bytes, const float *init_potentials, void *hip_stream) {
     if (jt_status rc = check_tree(t)) return rc;
     if (!init_potentials) return set_err(JT_E_ARG, "init_potentials is NULL");
+    if (t->is_bn) return set_err(JT_E_STATE, "a network tree is bound with jt_bind_bn");
+    // a merged tree's tables are the products of the caller's tables
+    if (t->is_merged) return bind_families(t, workspace, bytes, init_potentials, hip_stream);
     return bind_common(t, workspace, bytes, init_potentials, hip_stream);
 }
 
@@ -601,6 +640,13 @@ jt_status jt_bind_bn(jt_tree t, void *workspace, size_t bytes, const float *cpts
     if (jt_status rc = check_tree(t)) return rc;
     if (!t->is_bn) return set_err(JT_E_STATE, "not a network tree");
     if (!cpts) return set_err(JT_E_ARG, "cpts is NULL");
+    return bind_families(t, workspace, bytes, cpts, hip_stream);
+}
+
+// Bind, then compute every clique's table as the product of its families'
+// tables (the conditional tables of a network, or a merged tree's original
+// clique tables), and upload the families' mapping lists.
+jt_status bind_families(jt_tree t, void *workspace, size_t bytes, const float *cpts, void *hip_stream) {
     if (jt_status rc = bind_common(t, workspace, bytes, nullptr, hip_stream)) return rc;
     const jt::Plan &P = t->plan;
     hipError_t e = hipSuccess;
@@ -662,10 +708,11 @@ jt_status jt_bn_expected_counts(jt_tree t, int32_t n_active, float *counts) {
     if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
     if (n_active < 1 || n_active > t->last_n_active) return set_err(JT_E_STATE, "slots not active in the last propagation");
     const jt::Plan &P = t->plan;
-    hipError_t e = jt_launch_bn_counts(t->dev, reinterpret_cast<const JtFamily *>(t->ws + P.off_fam), (int)P.fam.size(),
-                                       P.max_fsize, reinterpret_cast<const int32_t *>(t->ws + P.off_fam_mu),
-                                       reinterpret_cast<const JtCliqueShape *>(t->ws + P.off_cshape), n_active, counts,
-                                       t->stream);
+    hipError_t e = jt_launch_family_marginal(t->dev, reinterpret_cast<const JtFamily *>(t->ws + P.off_fam), 0,
+                                             (int)P.fam.size(), P.max_fsize,
+                                             reinterpret_cast<const int32_t *>(t->ws + P.off_fam_mu),
+                                             reinterpret_cast<const JtCliqueShape *>(t->ws + P.off_cshape), 0, n_active,
+                                             counts, 0, t->stream);
     if (e != hipSuccess) return hip_err(e, "expected counts launch");
     return JT_OK;
 }
@@ -726,16 +773,53 @@ jt_status jt_propagate(jt_tree t, int32_t mode) {
     return jt_propagate_n(t, mode, t->plan.n_slots);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Merged trees: the posteriors of original cliques [c0, c0 + n) of one slot,
+// marginalized from their merged cliques into the staging region, then
+// copied to `out` (host or device).
+jt_status merged_read(jt_tree t, int32_t slot, int32_t c0, int32_t n, float *out) {
+    const jt::Plan &P = t->plan;
+    const JtFamily *fam = reinterpret_cast<const JtFamily *>(t->ws + P.off_fam);
+    float *stage = reinterpret_cast<float *>(t->ws + P.off_stage);
+    // families are sorted by merged clique: find the records of c0 .. c0+n-1
+    hipError_t e = hipSuccess;
+    int64_t lo = -1, hi = -1;
+    for (size_t k = 0; k < P.fam.size() && e == hipSuccess; ++k) {
+        const int32_t oc = P.fam[k].var;
+        if (oc < c0 || oc >= c0 + n) continue;
+        e = jt_launch_family_marginal(t->dev, fam, (int)k, 1, P.fam[k].fsize,
+                                      reinterpret_cast<const int32_t *>(t->ws + P.off_fam_mu),
+                                      reinterpret_cast<const JtCliqueShape *>(t->ws + P.off_cshape), slot, 1, stage, 0,
+                                      t->stream);
+        lo = lo < 0 ? P.fam[k].cpt_off : std::min<int64_t>(lo, P.fam[k].cpt_off);
+        hi = std::max<int64_t>(hi, P.fam[k].cpt_off + P.fam[k].fsize);
+    }
+    if (e == hipSuccess && lo >= 0)
+        e = hipMemcpyAsync(out, stage + lo, (size_t)(hi - lo) * sizeof(float), hipMemcpyDefault, t->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+    if (e != hipSuccess) return hip_err(e, "merged read-out");
+    return JT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 jt_status jt_marginal(jt_tree t, int32_t slot, int32_t clique, float *out, double *log_z) {
     if (jt_status rc = check_tree(t)) return rc;
     const jt::Plan &P = t->plan;
     if (slot < 0 || slot >= P.n_slots) return set_err(JT_E_ARG, "slot out of range");
-    if (clique < 0 || clique >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");
+    const int32_t n_user = t->is_merged ? (int32_t)t->merged.orig_size.size() : P.n_cliques;
+    if (clique < 0 || clique >= n_user) return set_err(JT_E_ARG, "clique out of range");
     if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
     if (slot >= t->last_n_active) return set_err(JT_E_STATE, "slot was not active in the last propagation");
     bool zero = false;
     if (jt_status rc = read_slot(t, slot, log_z, &zero)) return rc;
     if (zero) return set_err(JT_E_ZERO_EVIDENCE, "evidence has probability zero");
+    if (out && t->is_merged) return merged_read(t, slot, clique, 1, out);
     if (out) {
         const jt::CliqueInfo &C = P.cl[clique];
         hipError_t e = hipMemcpy(out, t->ws + P.off_out + ((size_t)slot * P.out_stride + C.out_off) * sizeof(float),
@@ -754,6 +838,7 @@ jt_status jt_marginals_all(jt_tree t, int32_t slot, float *out, double *log_z) {
     bool zero = false;
     if (jt_status rc = read_slot(t, slot, log_z, &zero)) return rc;
     if (zero) return set_err(JT_E_ZERO_EVIDENCE, "evidence has probability zero");
+    if (out && t->is_merged) return merged_read(t, slot, 0, (int32_t)t->merged.orig_size.size(), out);
     if (out) {
         int64_t dst = 0;
         for (int32_t c = 0; c < P.n_cliques; ++c) {
@@ -873,8 +958,18 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
     };
     switch (what) {
         case JT_Q_N_SLOTS: *out = P.n_slots; break;
-        case JT_Q_TOTAL_ENTRIES: *out = P.total_entries; break;
+        case JT_Q_TOTAL_ENTRIES: *out = t->is_merged ? t->merged.total : P.total_entries; break;
         case JT_Q_TABLE_SIZE:
+            if (t->is_merged) {
+                if (arg < 0 || arg >= (int64_t)t->merged.orig_size.size()) return set_err(JT_E_ARG, "clique out of range");
+                *out = t->merged.orig_size[arg];
+                break;
+            }
+            if (arg < 0 || arg >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");
+            *out = P.cl[arg].size;
+            break;
+        case JT_Q_N_COMPILED_CLIQUES: *out = P.n_cliques; break;
+        case JT_Q_COMPILED_TABLE_SIZE:
             if (arg < 0 || arg >= P.n_cliques) return set_err(JT_E_ARG, "clique out of range");
             *out = P.cl[arg].size;
             break;

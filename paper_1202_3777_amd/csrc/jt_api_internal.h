@@ -60,6 +60,9 @@ struct jt_tree_s {
     // Bayesian-network trees: the compiled network (cliques, families)
     bool is_bn = false;
     jt::BnTree bn;
+    // merged trees: the caller's cliques are families of the compiled ones
+    bool is_merged = false;
+    jt::MergedTree merged;
     // paper-faithful schedule: its plan, its workspace (mapping lists,
     // message and block records), layout and threads per block
     jt::PaperPlan paper;

@@ -35,24 +35,26 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_bn_init_kernel(
     }
 }
 
-// Block (entry chunk, family): thread j sums the family's marginal entry j
-// over slots [0, n_active), then over the clique entries of list j in
-// ascending order, in FP64.
-extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_bn_counts_kernel(
-    const JtFamily *__restrict__ fam, const int32_t *__restrict__ mu, const int64_t *__restrict__ cltab,
-    const float *__restrict__ out, int64_t out_stride, int n_active, const JtCliqueShape *__restrict__ shape,
-    float *__restrict__ counts) {
-    const JtFamily F = fam[blockIdx.y];
+// Block (entry chunk, family fam0 + y): thread j sums entry j of the family's
+// marginal of the calibrated clique over slots [s0, s0 + n_slots), then over
+// the clique entries of list j in ascending order, in FP64, into
+// dst[cpt_off - dst_base + j].  Expected counts (all active slots) and the
+// read-out of merged cliques' original cliques (one slot) both use it.
+extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_family_marginal_kernel(
+    const JtFamily *__restrict__ fam, int fam0, const int32_t *__restrict__ mu, const int64_t *__restrict__ cltab,
+    const float *__restrict__ out, int64_t out_stride, int s0, int n_slots, const JtCliqueShape *__restrict__ shape,
+    float *__restrict__ dst, int64_t dst_base) {
+    const JtFamily F = fam[fam0 + blockIdx.y];
     const int64_t j = (int64_t)blockIdx.x * JT_BLOCK + threadIdx.x;
     if (j >= F.fsize) return;
     const int64_t m = shape[F.clique].size / F.fsize;
     const int32_t *__restrict__ list = mu + F.mu_off + j * m;
     double acc = 0.0;
-    for (int s = 0; s < n_active; ++s) {
+    for (int s = s0; s < s0 + n_slots; ++s) {
         const float *__restrict__ post = out + (int64_t)s * out_stride + cltab[3 * F.clique];
         for (int64_t n = 0; n < m; ++n) acc += (double)post[list[n]];
     }
-    counts[F.cpt_off + j] = (float)acc;
+    dst[F.cpt_off - dst_base + j] = (float)acc;
 }
 
 hipError_t jt_launch_bn_init(const JtDev &d, const JtFamily *fam, const int32_t *fam_rng, const JtCliqueShape *shape,
@@ -63,11 +65,12 @@ hipError_t jt_launch_bn_init(const JtDev &d, const JtFamily *fam, const int32_t 
     return hipGetLastError();
 }
 
-hipError_t jt_launch_bn_counts(const JtDev &d, const JtFamily *fam, int n_fam, int64_t max_fsize, const int32_t *mu,
-                               const JtCliqueShape *shape, int n_active, float *counts, hipStream_t s) {
+hipError_t jt_launch_family_marginal(const JtDev &d, const JtFamily *fam, int fam0, int n_fam, int64_t max_fsize,
+                                     const int32_t *mu, const JtCliqueShape *shape, int s0, int n_slots, float *dst,
+                                     int64_t dst_base, hipStream_t s) {
     const unsigned gx = (unsigned)((max_fsize + JT_BLOCK - 1) / JT_BLOCK);
-    hipLaunchKernelGGL(jt_bn_counts_kernel, dim3(gx, (unsigned)n_fam), dim3(JT_BLOCK), 0, s, fam, mu, d.cltab, d.out,
-                       d.out_stride, n_active, shape, counts);
+    hipLaunchKernelGGL(jt_family_marginal_kernel, dim3(gx, (unsigned)n_fam), dim3(JT_BLOCK), 0, s, fam, fam0, mu,
+                       d.cltab, d.out, d.out_stride, s0, n_slots, shape, dst, dst_base);
     return hipGetLastError();
 }
 

@@ -1292,6 +1292,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err, cons
         P.off_fam_mu = region((size_t)P.fam_mu_total * sizeof(int32_t));
         P.off_cshape = region(P.cshape.size() * sizeof(JtCliqueShape));
         P.off_card = region(std::max<size_t>(1, P.card.size()) * sizeof(int32_t));
+        P.stage_floats = cpt_total;
+        P.off_stage = region((size_t)std::max<int64_t>(1, cpt_total) * sizeof(float));
     }
     P.total_bytes = off;
     P.slot_bytes = (size_t)P.coll_stride * sizeof(float) + (size_t)P.out_stride * sizeof(float) +
@@ -1789,6 +1791,109 @@ jt_status compile_bn(const jt_bn_desc *bn, BnTree &T, std::string &err) {
         off += size;
     }
     T.cpt_total = off;
+    return JT_OK;
+}
+
+jt_status merge_tree(const jt_tree_desc *desc, int32_t max_sep, int64_t max_entries, MergedTree &M,
+                     std::string &err) {
+    M = MergedTree();
+    {
+        // the caller's tree must be a junction tree
+        Plan check;
+        jt_tree_desc d1 = *desc;
+        d1.n_slots = 1;
+        d1.tuning = nullptr;
+        const jt_status rc = compile_plan(&d1, check, err);
+        if (rc != JT_OK) return rc;
+    }
+    if (max_sep < 1 || max_entries < 1) return fail(err, JT_E_ARG, "merge bounds must be positive");
+    const int32_t nc = desc->n_cliques, nv = desc->n_vars;
+    M.card.assign(desc->card, desc->card + nv);
+    std::vector<std::vector<int32_t>> vars(nc);
+    for (int32_t c = 0; c < nc; ++c) {
+        vars[c].assign(desc->clique_vars + desc->clique_off[c], desc->clique_vars + desc->clique_off[c + 1]);
+        int64_t sz = 1;
+        for (int32_t v : vars[c]) sz *= M.card[v];
+        M.orig_size.push_back(sz);
+    }
+    int32_t root = -1;
+    std::vector<std::vector<int32_t>> ch(nc);
+    for (int32_t c = 0; c < nc; ++c) {
+        if (desc->parent[c] < 0) root = c;
+        else ch[desc->parent[c]].push_back(c);
+    }
+    // post-order (children ascending)
+    std::vector<int32_t> post;
+    {
+        std::vector<std::pair<int32_t, size_t>> st{{root, 0}};
+        while (!st.empty()) {
+            auto &top = st.back();
+            if (top.second < ch[top.first].size()) {
+                const int32_t c = ch[top.first][top.second++];
+                st.push_back({c, 0});
+            } else {
+                post.push_back(top.first);
+                st.pop_back();
+            }
+        }
+    }
+    std::vector<int32_t> grp(nc);
+    std::vector<std::vector<int32_t>> gvars(nc);   // sorted union of each group's variables
+    for (int32_t c = 0; c < nc; ++c) {
+        grp[c] = c;
+        gvars[c] = vars[c];
+        std::sort(gvars[c].begin(), gvars[c].end());
+    }
+    std::function<int32_t(int32_t)> find = [&](int32_t x) { return grp[x] == x ? x : (grp[x] = find(grp[x])); };
+    for (int32_t c : post) {
+        const int32_t p = desc->parent[c];
+        if (p < 0) continue;
+        std::vector<int32_t> sc(vars[c]), sp(vars[p]), sep;
+        std::sort(sc.begin(), sc.end());
+        std::sort(sp.begin(), sp.end());
+        std::set_intersection(sc.begin(), sc.end(), sp.begin(), sp.end(), std::back_inserter(sep));
+        int64_t ss = 1;
+        for (int32_t v : sep) ss *= M.card[v];
+        if (ss > max_sep) continue;
+        const int32_t a = find(c), b = find(p);
+        std::vector<int32_t> un;
+        std::set_union(gvars[a].begin(), gvars[a].end(), gvars[b].begin(), gvars[b].end(), std::back_inserter(un));
+        int64_t sz = 1;
+        for (int32_t v : un) {
+            sz *= M.card[v];
+            if (sz > max_entries) break;
+        }
+        if (sz > max_entries) continue;
+        grp[a] = b;
+        gvars[b] = un;
+    }
+    // merged cliques in order of their smallest original id (the caller's
+    // root's group first)
+    std::vector<int32_t> id(nc, -1), rep;
+    const int32_t r0 = find(root);
+    id[r0] = 0;
+    rep.push_back(r0);
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t g = find(c);
+        if (id[g] < 0) {
+            id[g] = (int32_t)rep.size();
+            rep.push_back(g);
+        }
+    }
+    const int32_t nm = (int32_t)rep.size();
+    M.cliques.resize(nm);
+    M.parent.assign(nm, -1);
+    for (int32_t k = 0; k < nm; ++k) M.cliques[k] = gvars[rep[k]];
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t p = desc->parent[c];
+        if (p >= 0 && find(c) != find(p)) M.parent[id[find(c)]] = id[find(p)];
+    }
+    int64_t off = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        M.families.push_back({id[find(c)], c, vars[c], off});
+        off += M.orig_size[c];
+    }
+    M.total = off;
     return JT_OK;
 }
 

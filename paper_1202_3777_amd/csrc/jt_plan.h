@@ -141,6 +141,9 @@ struct Plan {
     std::vector<JtCliqueShape> cshape;   // per clique (network trees)
     int64_t max_tiles = 0, max_fsize = 0;
     size_t off_fam = 0, off_fam_rng = 0, off_fam_mu = 0, off_cshape = 0, off_card = 0;
+    // merged trees: read-out staging of one slot's original-clique posteriors
+    int64_t stage_floats = 0;
+    size_t off_stage = 0;
     size_t slot_bytes = 0;           // workspace bytes that scale with the slot count (per slot)
 
     // statistics
@@ -186,6 +189,23 @@ struct BnTree {
     int64_t cpt_total = 0;
 };
 jt_status compile_bn(const jt_bn_desc *bn, BnTree &out, std::string &err);
+
+// Merging small separators (the paper's Sec. 5): contract every edge whose
+// separator has at most max_sep entries, bottom-up from the caller's
+// root, while the merged clique's table stays within max_entries.  Each
+// merged clique lists the union of its cliques' variables ascending; the
+// original cliques become its "families" (their tables multiplied into it,
+// their posteriors read back out of it).  The caller's tree is validated.
+struct MergedTree {
+    std::vector<int32_t> card;
+    std::vector<std::vector<int32_t>> cliques;
+    std::vector<int32_t> parent;
+    std::vector<FamilyReq> families;     // var = original clique id
+    std::vector<int64_t> orig_size;      // per original clique
+    int64_t total = 0;                   // sum of the original table sizes
+};
+jt_status merge_tree(const jt_tree_desc *desc, int32_t max_sep, int64_t max_entries, MergedTree &out,
+                     std::string &err);
 
 // Per-propagation schedule of a batched tree: which (clique, slot) pairs the
 // collect sweep computes and where every slot reads collect data from.

@@ -61,11 +61,13 @@ JT_Q_LAST_SHARED = 20
 JT_Q_LAST_COLLECT_PASSES = 21
 JT_Q_TOTAL_CLIQUE_VARS = 22
 JT_Q_CPT_TOTAL = 23
+JT_Q_N_COMPILED_CLIQUES = 24
+JT_Q_COMPILED_TABLE_SIZE = 25
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_read_out", "jt_paper_bytes", "jt_paper_bind", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
             "jt_propagate_scratch", "jt_compile_bn", "jt_bn_structure", "jt_bind_bn", "jt_bn_expected_counts",
-            "jt_bn_m_step", "jt_bn_set_cpts", "jt_free", "jt_last_error"]
+            "jt_bn_m_step", "jt_bn_set_cpts", "jt_compile_merged", "jt_free", "jt_last_error"]
 
 
 class JTError(RuntimeError):
@@ -131,10 +133,13 @@ def load():
     lib.jt_bn_expected_counts.argtypes = [V, I32, V]
     lib.jt_bn_m_step.argtypes = [V, V, ctypes.c_float, V]
     lib.jt_bn_set_cpts.argtypes = [V, V]
+    lib.jt_compile_merged.argtypes = [ctypes.POINTER(jt_tree_desc), I32, I64, ctypes.POINTER(V), ctypes.POINTER(SZ),
+                                      P32]
     for f in ("jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
               "jt_marginals_all", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
               "jt_propagate_scratch", "jt_read_out", "jt_paper_bytes", "jt_paper_bind", "jt_compile_bn",
-              "jt_bn_structure", "jt_bind_bn", "jt_bn_expected_counts", "jt_bn_m_step", "jt_bn_set_cpts"):
+              "jt_bn_structure", "jt_bind_bn", "jt_bn_expected_counts", "jt_bn_m_step", "jt_bn_set_cpts",
+              "jt_compile_merged"):
         getattr(lib, f).restype = I32
     lib.jt_free.argtypes = [V]
     lib.jt_free.restype = None
@@ -176,6 +181,25 @@ def jt_compile_index_maps(card, clique_off, clique_vars, parent, n_slots: int = 
     _check(lib.jt_compile_index_maps(ctypes.byref(d), ctypes.byref(h), ctypes.byref(nbytes)),
            "jt_compile_index_maps")
     return h, int(nbytes.value)
+
+
+def jt_compile_merged(card, clique_off, clique_vars, parent, max_sep: int, max_entries: int, n_slots: int = 1,
+                      tuning: Optional[dict] = None):
+    """Returns (handle, device_bytes, n_compiled): the tree with its small
+    separators merged away (see include/jt.h)."""
+    lib = load()
+    card = np.ascontiguousarray(card, dtype=np.int32)
+    off = np.ascontiguousarray(clique_off, dtype=np.int64)
+    cv = np.ascontiguousarray(clique_vars, dtype=np.int32)
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    d = jt_tree_desc(int(card.shape[0]), _p(card, ctypes.c_int32), int(par.shape[0]), _p(off, ctypes.c_int64),
+                     _p(cv, ctypes.c_int32), _p(par, ctypes.c_int32), int(n_slots), _tuning_ptr(tuning))
+    h = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    nm = ctypes.c_int32()
+    _check(lib.jt_compile_merged(ctypes.byref(d), int(max_sep), int(max_entries), ctypes.byref(h),
+                                 ctypes.byref(nbytes), ctypes.byref(nm)), "jt_compile_merged")
+    return h, int(nbytes.value), int(nm.value)
 
 
 def jt_bind(h, workspace_ptr: int, nbytes: int, init_ptr: int, stream_ptr: int):
@@ -335,7 +359,10 @@ def jt_last_error() -> str:
 class JunctionTreePlan:
     """A compiled tree (host side only): index maps and schedule facts."""
 
-    def __init__(self, card, clique_off, clique_vars, parent, n_slots: int = 1, tuning: Optional[dict] = None):
+    def __init__(self, card, clique_off, clique_vars, parent, n_slots: int = 1, tuning: Optional[dict] = None,
+                 merge: Optional[Tuple[int, int]] = None):
+        """merge=(max_sep, max_entries): compile with small separators merged
+        away (jt_compile_merged); the interface stays the caller's cliques."""
         self.tuning = dict(tuning) if tuning else {}
         self.card = np.ascontiguousarray(card, dtype=np.int32)
         self.clique_off = np.ascontiguousarray(clique_off, dtype=np.int64)
@@ -343,16 +370,20 @@ class JunctionTreePlan:
         self.parent = np.ascontiguousarray(parent, dtype=np.int32)
         self.n_cliques = int(self.parent.shape[0])
         self.n_slots = int(n_slots)
-        self.handle, self.device_bytes = jt_compile_index_maps(self.card, self.clique_off, self.clique_vars,
-                                                               self.parent, n_slots, self.tuning)
+        if merge is None:
+            self.handle, self.device_bytes = jt_compile_index_maps(self.card, self.clique_off, self.clique_vars,
+                                                                   self.parent, n_slots, self.tuning)
+        else:
+            self.handle, self.device_bytes, self.n_compiled = jt_compile_merged(
+                self.card, self.clique_off, self.clique_vars, self.parent, merge[0], merge[1], n_slots, self.tuning)
         self.table_size = np.asarray([jt_query(self.handle, JT_Q_TABLE_SIZE, c) for c in range(self.n_cliques)],
                                      dtype=np.int64)
         self.table_off = np.concatenate([[0], np.cumsum(self.table_size)]).astype(np.int64)
 
     @classmethod
-    def from_instance(cls, inst, n_slots: Optional[int] = None, tuning: Optional[dict] = None):
+    def from_instance(cls, inst, n_slots: Optional[int] = None, tuning: Optional[dict] = None, merge=None):
         return cls(inst.card, inst.clique_off, inst.clique_vars, inst.parent,
-                   n_slots if n_slots is not None else max(1, inst.n_slots), tuning)
+                   n_slots if n_slots is not None else max(1, inst.n_slots), tuning, merge)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -377,9 +408,9 @@ class JunctionTree(JunctionTreePlan):
     """A compiled tree bound to torch-owned device memory on one stream."""
 
     def __init__(self, card, clique_off, clique_vars, parent, potentials: np.ndarray, n_slots: int = 1,
-                 device: str = "cuda", stream=None, tuning: Optional[dict] = None):
+                 device: str = "cuda", stream=None, tuning: Optional[dict] = None, merge=None):
         import torch
-        super().__init__(card, clique_off, clique_vars, parent, n_slots, tuning)
+        super().__init__(card, clique_off, clique_vars, parent, n_slots, tuning, merge)
         self.torch = torch
         self.device = torch.device(device)
         # a stream of its own: the legacy default stream cannot be captured

@@ -261,3 +261,29 @@ def test_autotuner_picks_the_fastest():
     assert [t for _, t in table] == [3.0, 2.0, 2.0]
     for c in tune.DEFAULT_CANDIDATES:            # every default candidate compiles
         jt.JunctionTreePlan.from_instance(make_instance("c1", 0), tuning=c)
+
+
+def test_merged_compile_structure():
+    # merging small separators: fewer compiled cliques, the caller's cliques
+    # stay the interface, bounds below 1 are refused
+    inst = make_instance("c1", 0)
+    h, nbytes, nm = jt.jt_compile_merged(inst.card, inst.clique_off, inst.clique_vars, inst.parent, 4, 4096)
+    assert 1 <= nm < inst.n_cliques
+    assert jt.jt_query(h, jt.JT_Q_N_COMPILED_CLIQUES) == nm
+    assert jt.jt_query(h, jt.JT_Q_TOTAL_ENTRIES) == inst.total_entries()
+    for c in range(inst.n_cliques):
+        assert jt.jt_query(h, jt.JT_Q_TABLE_SIZE, c) == inst.table_size(c)
+    assert all(jt.jt_query(h, jt.JT_Q_COMPILED_TABLE_SIZE, k) <= 4096 for k in range(nm))
+    jt.jt_free(h)
+    # nothing below the separator bound: the same number of cliques
+    h2, _, nm2 = jt.jt_compile_merged(inst.card, inst.clique_off, inst.clique_vars, inst.parent, 1, 1 << 20)
+    assert nm2 == inst.n_cliques
+    jt.jt_free(h2)
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_compile_merged(inst.card, inst.clique_off, inst.clique_vars, inst.parent, 0, 100)
+    assert ei.value.code == jt.JT_E_ARG
+    # a tree that is not a junction tree is refused before merging
+    bad = np.asarray([-1, -1] + list(inst.parent[2:]), np.int32)
+    with pytest.raises(jt.JTError) as ei:
+        jt.jt_compile_merged(inst.card, inst.clique_off, inst.clique_vars, bad, 4, 4096)
+    assert ei.value.code == jt.JT_E_NOT_JUNCTION_TREE

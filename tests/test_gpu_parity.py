@@ -336,3 +336,25 @@ def test_paper_schedule_parity_and_layouts():
             for s in range(tree.n_slots):
                 a, la = tree.marginals_all(s)
                 assert np.array_equal(a, first[s][0]) and la == first[s][1], (inst.name, layout, tpb, mode)
+
+
+def test_merged_small_separators():
+    # the paper's future work: small separators merged away; the caller's
+    # cliques' posteriors (marginalized from the merged cliques on the
+    # device) against the oracle on the unmerged tree
+    jt = _gpu()
+    cases = [(make_instance("c1", 0), (4, 4096)), (make_instance("c1", 1), (4, 1 << 16)),
+             (make_instance("c4", 2, n_slots=5), (8, 1 << 16)),
+             (make_instance("c3", 1, n_cliques=8), (32, 1 << 22)),
+             (from_arrays([2, 3, 4], [[0, 1], [2]], [-1, 0], seed=2, evidence=[([2], [1])]), (1, 64))]
+    for inst, merge in cases:
+        plan = oracle.Plan.from_instance(inst)
+        tree = jt.JunctionTree.from_instance(inst, merge=merge)
+        print(f"[merged] {inst.name}: {inst.n_cliques} cliques -> {tree.n_compiled}")
+        for mode in ("fused", "graph", "plain"):
+            tree.propagate(mode)
+            for s in range(tree.n_slots):
+                compare(tree, plan, inst, s, plan.run(inst.potentials, *inst.evidence[s]), f"{inst.name}/merged/{mode}")
+        one, _ = tree.marginal(0, inst.n_cliques - 1)
+        allm, _ = tree.marginals_all(0)
+        assert np.array_equal(one, allm[tree.table_off[-2]:tree.table_off[-1]])
