@@ -13,11 +13,15 @@ recomputed inside every step.
 Metric: BP table entries per second, counted as the numerator of the
 paper's per-message cost (|phi_Xi| + |phi_Xk| per message, both sweeps,
 every evidence set).  Also reported:
-  * roofline of the dominant kernel (the streaming pass kernel, the only
-    kernel of a propagation): FP32 table bytes the executed schedule moves
-    (shared tables once per launch) over the graph-replayed launch time, HIP
-    events on the tree's stream around the timed steps; against the 8 TB/s
-    HBM peak and a copy kernel measured in the same run;
+  * roofline of the dominant kernel (the streaming pass kernels -- the
+    one-slot and the multi-slot variant of one pass -- the only kernels of
+    a propagation): the algorithmic FP32 table bytes of a fused propagation
+    (per clique, evidence set and entry: 12 B for a leaf, 16 B for an inner
+    clique, 8 B for the root) over the graph-replayed launch time, HIP events
+    on the tree's stream around the timed steps, against the 8 TB/s HBM peak
+    and a copy kernel measured in the same run; beside it the bytes the
+    executed schedule moved (shared evidence-free collect tables make that
+    fewer) and the HBM traffic the counters measured;
   * the one-query-at-a-time GPU sweep (the paper's schedule: one message at a
     time, each evidence set alone) on the same 256 sets;
   * the error of every set against the FP64 oracle;
@@ -80,7 +84,7 @@ def parse():
 
 
 COPY_BYTES = 256 << 20
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "jt_pass_kernel_{cfg}_traffic.json")
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "jt_pass_{cfg}_traffic.json")
 
 
 def log(msg):
@@ -359,10 +363,17 @@ def main():
     # bracket the launches back to back, so the average launch time here
     # includes the gaps between them and bounds rocprof's kernel time above)
     avg_launch_ms = ms / n_launch
-    achieved = bytes_step / (ms * 1e-3) / 1e9
+    # algorithmic bytes (every slot computed on its own: per clique and entry
+    # 12 B for a leaf, 16 B for an inner clique, 8 B for the root; the unfused
+    # schedule's own bytes for the plain mode) and the bytes the executed
+    # schedule moved (shared tables counted once per launch)
+    alg_step = bytes_step if args.mode == "plain" else tree.query(jt.JT_Q_ALG_BYTES, 0)
+    achieved = alg_step / (ms * 1e-3) / 1e9
+    executed_gbs = bytes_step / (ms * 1e-3) / 1e9
     copy_gbs = copy_ceiling_gbs(torch)
-    log(f"[bench] {bytes_step / 1e6:.1f} MB per propagation in {n_launch} launches: {achieved:.0f} GB/s; "
-        f"copy kernel {copy_gbs:.0f} GB/s; shared collect {shared}, collect passes {collect_passes}")
+    log(f"[bench] algorithmic {alg_step / 1e6:.1f} MB per propagation ({achieved:.0f} GB/s); executed schedule "
+        f"{bytes_step / 1e6:.1f} MB in {n_launch} launches ({executed_gbs:.0f} GB/s); copy kernel {copy_gbs:.0f} GB/s; "
+        f"shared collect {shared}, collect passes {collect_passes}")
 
     # the paper's schedule, one evidence set at a time
     plain = None
@@ -454,11 +465,16 @@ def main():
                    "clique_slot_pairs": inst.n_cliques * n_slots},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.config, "jt_pass_kernel", tuning),
-                     "kernel": "jt_pass_kernel", "launches_per_step": n_launch,
-                     "avg_launch_us": avg_launch_ms * 1e3, "bytes_per_launch": bytes_step / n_launch,
-                     "bytes_per_step": bytes_step, "copy_kernel_gbs": copy_gbs,
-                     "frac_of_copy": achieved / copy_gbs},
+                     "traffic": measured_traffic(args.config, "jt_pass", tuning),
+                     "kernel": "jt_pass_kernel + jt_pass_multi_kernel (every launch of a propagation)",
+                     "launches_per_step": n_launch, "avg_launch_us": avg_launch_ms * 1e3,
+                     "bytes": "algorithmic: per clique, slot and table entry 12 B (leaf), 16 B (inner clique), "
+                              "8 B (root), FP32 values only" if args.mode != "plain" else
+                              "the one-message-at-a-time schedule's FP32 table bytes",
+                     "bytes_per_launch": alg_step / n_launch, "bytes_per_step": alg_step,
+                     "executed_bytes_per_step": bytes_step, "executed_gbs": executed_gbs,
+                     "executed_frac": executed_gbs / HBM_PEAK_GBS,
+                     "copy_kernel_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "plain_sweep": plain,
         "max_rel_err_vs_fp64": worst,
         "elem_rel_err_vs_fp64": elem,

@@ -98,9 +98,13 @@ typedef struct jt_tree_s *jt_tree;
  *                         round of resident blocks);
  *   max_lanes             streams for the root's subtrees (1 = all levels
  *                         on the bound stream); lanes are disabled in this
- *                         version: values above 1 return JT_E_ARG. */
+ *                         version: values above 1 return JT_E_ARG;
+ *   task_min              least work of one block (entries, written entries
+ *                         counted twice) before it takes a second group,
+ *                         default group_min; smaller values spread a small
+ *                         launch's groups over more blocks. */
 typedef struct {
-    int32_t group_min, group_max, group_div, target_blocks, max_lanes;
+    int32_t group_min, group_max, group_div, target_blocks, max_lanes, task_min;
 } jt_tuning;
 
 typedef struct {
@@ -351,9 +355,22 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *     tables, 0 otherwise),
  *   JT_Q_N_COMPILED_CLIQUES, JT_Q_COMPILED_TABLE_SIZE (arg = clique): the
  *     cliques the schedules run on (for a merged tree its merged cliques;
- *     JT_Q_TABLE_SIZE and JT_Q_TOTAL_ENTRIES describe the caller's).
+ *     JT_Q_TABLE_SIZE and JT_Q_TOTAL_ENTRIES describe the caller's),
+ *   JT_Q_LAST_LAUNCH_BYTES (arg = launch index, as for
+ *     JT_Q_FUSED_LAUNCH_BYTES: FP32 table bytes that launch moved in the last
+ *     JT_MODE_FUSED / JT_MODE_GRAPH propagation, counted as for
+ *     JT_Q_BYTES_LAST; a shared source table read by both of a level's
+ *     distribute launches is counted in the multi-slot one),
+ *   JT_Q_ALG_BYTES (arg = slot count, 0 = all: the FP32 table bytes a fused
+ *     propagation must move when every slot is computed on its own -- per
+ *     clique and entry 12 B for a leaf (initial table read twice, posterior
+ *     written), 16 B for an inner clique (its absorbed table written and read
+ *     back too), 8 B for the schedule's root (read once, written once) -- the
+ *     algorithmic count the roofline is priced on; shared evidence-free
+ *     collect messages make the executed schedule move fewer, JT_Q_BYTES_LAST).
  * JT_Q_BYTES_LAST, JT_Q_LAST_SHARED and JT_Q_LAST_COLLECT_PASSES return
- * JT_E_STATE before the first propagation.  Other errors: JT_E_ARG. */
+ * JT_E_STATE before the first propagation, JT_Q_LAST_LAUNCH_BYTES before the
+ * first fused or graph propagation.  Other errors: JT_E_ARG. */
 #define JT_Q_N_SLOTS 0
 #define JT_Q_TOTAL_ENTRIES 1
 #define JT_Q_TABLE_SIZE 2
@@ -380,6 +397,8 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_CPT_TOTAL 23
 #define JT_Q_N_COMPILED_CLIQUES 24
 #define JT_Q_COMPILED_TABLE_SIZE 25
+#define JT_Q_LAST_LAUNCH_BYTES 26
+#define JT_Q_ALG_BYTES 27
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and

@@ -399,6 +399,11 @@ jt_status run_graph(jt_tree t, int S, bool paper = false) {
 // Record what the propagation just enqueued moves (FP32 table bytes).
 void note_last(jt_tree t, int mode, int n_active) {
     const jt::Plan &P = t->plan;
+    t->last_launch_bytes.clear();
+    if (mode == JT_MODE_FUSED || mode == JT_MODE_GRAPH)
+        for (size_t k = 0; k < P.fused.size(); ++k)
+            if (P.fused[k].count > 0)
+                t->last_launch_bytes.push_back(P.share ? t->dyn.launch_bytes[k] : P.fused[k].bytes);
     if (mode == JT_MODE_PAPER || mode == JT_MODE_PAPER_GRAPH) {
         // tables: reset (init read, table written), each message reads the
         // sender and reads and writes the receiver, read-out reads and
@@ -987,6 +992,18 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
         case JT_Q_SLOT_BYTES: *out = (int64_t)P.slot_bytes; break;
         case JT_Q_SHARED_BYTES: *out = (int64_t)P.total_bytes - (int64_t)P.slot_bytes * P.n_slots; break;
         case JT_Q_ROOT: *out = P.root; break;
+        case JT_Q_ALG_BYTES: {
+            // FP32 bytes a fused propagation must move per slot, per clique
+            // and entry: a leaf reads its table twice and writes its
+            // posterior (12 B), an inner clique also writes its absorbed
+            // table (16 B), the root reads once and writes once (8 B)
+            if (arg < 0 || arg > P.n_slots) return set_err(JT_E_ARG, "slot count out of range");
+            int64_t b = 0;
+            for (int32_t c = 0; c < P.n_cliques; ++c)
+                b += P.cl[c].size * (c == P.root ? 8 : P.cl[c].children.empty() ? 12 : 16);
+            *out = b * (arg > 0 ? arg : P.n_slots);
+            break;
+        }
         case JT_Q_TOTAL_CLIQUE_VARS: {
             int64_t k = 0;
             for (const jt::CliqueInfo &C : P.cl) k += (int64_t)C.vars.size();
@@ -1022,6 +1039,13 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
         case JT_Q_LAST_COLLECT_PASSES:
             if (!t->propagated) return set_err(JT_E_STATE, "nothing propagated yet");
             *out = t->last_collect_pairs;
+            break;
+        case JT_Q_LAST_LAUNCH_BYTES:
+            if (!t->propagated || t->last_launch_bytes.empty())
+                return set_err(JT_E_STATE, "no fused propagation yet");
+            if (arg < 0 || arg >= (int64_t)t->last_launch_bytes.size())
+                return set_err(JT_E_ARG, "launch index out of range");
+            *out = t->last_launch_bytes[arg];
             break;
         default: return set_err(JT_E_ARG, "unknown query");
     }

@@ -44,6 +44,7 @@ struct jt_tree_s {
     int64_t last_bytes = 0;
     int last_shared = 0;
     int64_t last_collect_pairs = 0;
+    std::vector<int64_t> last_launch_bytes;   // per live fused launch (fused and graph modes)
     // host copies the scratch entry point uploads from (kept until its next call)
     std::vector<int32_t> sx_ev_idx;
     std::vector<JtEv> sx_ev_ent;

@@ -103,8 +103,16 @@ typedef struct {
     int32_t msg;                // message this pass produces and finalizes, -1 none
     int32_t wave_groups;        // 1: short groups (one kept-outer configuration each,
                                 // all its tiles), each streamed whole by one wave
-    int32_t pad;
+    int32_t x_lds;              // gathers past the first JT_NG_REG: float offset in the dynamic
+                                // LDS of their staged tables (JT_X_LDS_FLOATS), -1: read from
+                                // global memory tile by tile
 } JtItem;
+
+/* LDS the gathers past the first JT_NG_REG of an item take (x = their
+ * number, T = the tile): Jin [x][T], per wave the Jout of its current 64
+ * tiles [waves][x][64], and per gather its ratio location [x][2] (LDS offset
+ * or -1, global offset). */
+#define JT_X_LDS_FLOATS(x, T) ((x) * (T) + JT_WAVES_PER_BLOCK * (x) * JT_WAVE + 2 * (x))
 
 // A block's share of an item: groups [g0, g1), one after the other.
 typedef struct {

@@ -272,7 +272,8 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1, int64_t target_blocks) {
     const int64_t extra = (int64_t)(i1 - i0) * P.n_slots;
     const bool few = extra < tb / 2;
     const int64_t budget = few ? tb - extra : tb;
-    const int64_t target = std::max<int64_t>(P.tune.group_min, few ? (entries + budget - 1) / budget : entries / budget);
+    const int64_t floor_ = P.tune.task_min > 0 ? P.tune.task_min : P.tune.group_min;
+    const int64_t target = std::max<int64_t>(floor_, few ? (entries + budget - 1) / budget : entries / budget);
     for (int32_t i = i0; i < i1; ++i) {
         const int64_t ge = (int64_t)P.items[i].tpg * P.items[i].T * weight(i);   // work of a full group
         const int64_t want = few ? (target + ge - 1) / ge : target / ge;
@@ -330,6 +331,17 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         P.gathers.push_back(G);
     }
     it.n_gather_lds = n_lds;
+    it.x_lds = -1;
+    if (it.n_gather > JT_NG_REG) {
+        // the Jin tables, per-tile Jout values and ratio locations of the
+        // gathers past the register ones, staged in LDS after the ratio tables
+        const int32_t x0 = (int32_t)align_up(lds, 4);
+        const int32_t xn = JT_X_LDS_FLOATS(it.n_gather - JT_NG_REG, C.T);
+        if (x0 + xn <= JT_LDS_RATIO_FLOATS) {
+            it.x_lds = x0;
+            lds = x0 + xn;
+        }
+    }
     it.lds_floats = lds;
     it.scale_clique = scale_clique;
     it.ev = (src_kind == JT_SRC_INIT) ? 1 : 0;
@@ -442,6 +454,17 @@ bool verify_plan(const Plan &P, std::string &why) {
         }
         if (it.gather_base < 0 || it.gather_base + it.n_gather > (int32_t)P.gathers.size()) return bad("gather range");
         if (it.n_gather_lds > it.n_gather || it.lds_floats > JT_LDS_RATIO_FLOATS) return bad("LDS budget");
+        if (it.x_lds >= 0) {
+            if (it.n_gather <= JT_NG_REG || it.x_lds % 4 != 0 ||
+                it.x_lds + (int64_t)JT_X_LDS_FLOATS(it.n_gather - JT_NG_REG, it.T) > it.lds_floats)
+                return bad("extra gather LDS range");
+            for (int32_t g = 0; g < it.n_gather; ++g) {
+                const JtGather &G = P.gathers[it.gather_base + g];
+                if (G.lds_off >= 0 && G.lds_off + G.ssize > it.x_lds) return bad("extra gathers overlap ratio tables");
+            }
+        } else if (it.x_lds != -1) {
+            return bad("extra gather LDS offset");
+        }
         for (int g = 0; g < it.n_gather; ++g) {
             const JtGather &G = P.gathers[it.gather_base + g];
             if (G.view < 0 || G.view >= (int32_t)P.views.size() || P.views[G.view].clique != it.clique) return bad("gather view");
@@ -592,17 +615,18 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err, cons
         return fail(err, JT_E_ARG, "NULL array in desc");
     P = Plan();
     {
-        jt_tuning d{JT_GROUP_MIN, JT_GROUP_MAX, JT_GROUP_DIV, JT_TARGET_BLOCKS, JT_LANES_ENABLED ? JT_MAX_LANES : 1};
+        jt_tuning d{JT_GROUP_MIN, JT_GROUP_MAX, JT_GROUP_DIV, JT_TARGET_BLOCKS, JT_LANES_ENABLED ? JT_MAX_LANES : 1, 0};
         if (desc->tuning) {
             const jt_tuning &u = *desc->tuning;
             if (u.group_min < 0 || u.group_max < 0 || u.group_div < 0 || u.target_blocks < 0 || u.max_lanes < 0 ||
-                u.max_lanes > JT_MAX_LANES || u.group_div > (1 << 20) || u.target_blocks > (1 << 20))
+                u.max_lanes > JT_MAX_LANES || u.group_div > (1 << 20) || u.target_blocks > (1 << 20) || u.task_min < 0)
                 return fail(err, JT_E_ARG, "tuning value out of range");
             if (u.group_min) d.group_min = u.group_min;
             if (u.group_max) d.group_max = u.group_max;
             if (u.group_div) d.group_div = u.group_div;
             if (u.target_blocks) d.target_blocks = u.target_blocks;
             if (u.max_lanes) d.max_lanes = u.max_lanes;
+            if (u.task_min) d.task_min = u.task_min;
         }
         if (d.group_min > d.group_max) return fail(err, JT_E_ARG, "tuning: group_min above group_max");
         if (!JT_LANES_ENABLED && d.max_lanes > 1)
@@ -1387,8 +1411,13 @@ void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_va
     for (int k = 0; k < JT_MS; ++k) none.s[k] = -1;
     D.chunks.assign((size_t)std::max<int64_t>(1, P.chunk_total), none);
     int64_t bytes = 0;
-    for (const Launch &l : P.fused) {
+    D.launch_bytes.assign(P.fused.size(), 0);
+    for (size_t li = 0; li < P.fused.size(); ++li) {
+        const Launch &l = P.fused[li];
         if (l.count == 0) continue;
+        int64_t bytes0 = bytes;
+        // the level's multi-slot launch directly precedes its other distribute launch
+        const int32_t mli = (li > 0 && P.fused[li - 1].multi && P.fused[li - 1].begin == l.begin) ? (int32_t)li - 1 : -1;
         if (l.listed && l.multi) {
             // sets of up to JT_MS slots per (task, clique without evidence of
             // them); all sets of one task go to one XCD (blocks are dealt to
@@ -1495,20 +1524,34 @@ void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_va
                 if (n > 0) bytes += tb;                          // initial table
                 if (it.dst_kind != JT_DST_NONE) bytes += tb * n;  // absorbed tables
             } else {
-                if (it.src_kind == JT_SRC_INIT) {
-                    bytes += tb;
-                } else {
-                    int64_t own = 0;
-                    bool any_shared = false;
-                    for (int32_t s = 0; s < n_active; ++s) {
-                        if (!shared_src(s, c)) ++own;
-                        else any_shared = true;
-                    }
-                    bytes += tb * (own + (any_shared ? 1 : 0));
+                // slots reading the shared source run in the level's
+                // multi-slot launch when the item is eligible, else here
+                // (shared source: the initial table, or the evidence-free
+                // slot's absorbed table; read once per launch that reads it)
+                int64_t own = 0, sh = 0;
+                for (int32_t s = 0; s < n_active; ++s) {
+                    if (!shared_src(s, c)) ++own;
+                    else ++sh;
                 }
-                if (it.dst_kind != JT_DST_NONE) bytes += tb * n_active;
+                const bool in_multi = share && P.item_multi[i] && sh > 0 && mli >= 0;
+                int64_t b_here = 0, b_multi = 0;
+                if (it.src_kind == JT_SRC_INIT) {
+                    if (own > 0 || !in_multi) b_here += tb;
+                    if (in_multi) b_multi += tb;
+                } else {
+                    b_here += tb * own;
+                    (in_multi ? b_multi : b_here) += sh > 0 ? tb : 0;
+                }
+                if (it.dst_kind != JT_DST_NONE) {
+                    b_here += tb * (in_multi ? own : n_active);
+                    if (in_multi) b_multi += tb * sh;
+                }
+                bytes += b_here + b_multi;
+                if (mli >= 0) D.launch_bytes[mli] += b_multi;
+                bytes0 += b_multi;
             }
         }
+        D.launch_bytes[li] = bytes - bytes0;
     }
     D.bytes = bytes;
     (void)S;

@@ -217,6 +217,7 @@ struct Dynamic {
     std::vector<int32_t> grid;          // [n_listed] blocks launched: the count rounded up to a power of
                                         // two (at most the list's capacity), so few graphs cover many counts
     int64_t bytes = 0;                  // FP32 table bytes of the fused propagation it describes
+    std::vector<int64_t> launch_bytes;  // [fused launches] the same per launch
     int32_t shared = 0;                 // 1: the evidence-free slot is computed and read
     int64_t collect_pairs = 0;          // (clique, slot) collect passes, evidence-free slot included
 };

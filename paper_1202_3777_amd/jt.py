@@ -63,6 +63,8 @@ JT_Q_TOTAL_CLIQUE_VARS = 22
 JT_Q_CPT_TOTAL = 23
 JT_Q_N_COMPILED_CLIQUES = 24
 JT_Q_COMPILED_TABLE_SIZE = 25
+JT_Q_LAST_LAUNCH_BYTES = 26
+JT_Q_ALG_BYTES = 27
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_read_out", "jt_paper_bytes", "jt_paper_bind", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",
@@ -78,7 +80,7 @@ class JTError(RuntimeError):
 
 class jt_tuning(ctypes.Structure):
     _fields_ = [("group_min", ctypes.c_int32), ("group_max", ctypes.c_int32), ("group_div", ctypes.c_int32),
-                ("target_blocks", ctypes.c_int32), ("max_lanes", ctypes.c_int32)]
+                ("target_blocks", ctypes.c_int32), ("max_lanes", ctypes.c_int32), ("task_min", ctypes.c_int32)]
 
 
 TUNING_FIELDS = [f for f, _ in jt_tuning._fields_]

@@ -3,16 +3,20 @@
     python -m paper_1202_3777_amd.rocprof_summary stats DIR
         per-kernel calls / average / total from a --kernel-trace --stats run
     python -m paper_1202_3777_amd.rocprof_summary launches DIR --config CFG [--tuning JSON]
-        launch by launch of the last fused propagation in a --kernel-trace run
-        of bench.py: grid, start, duration, FP32 table bytes (from the plan,
-        host only) and the bytes / duration rate
-    python -m paper_1202_3777_amd.rocprof_summary traffic --kernel NAME \\
-        --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N \\
-        [--launches-per-step K] --out FILE.json
-        HBM bytes per launch of NAME from two counter runs (FETCH_SIZE, then
-        WRITE_SIZE), each scaled by what the same counter reads for a plain
-        copy of N bytes (torch copy kernel) so that the counter's unit and
-        coverage are calibrated on this GPU.
+        launch by launch of the last propagation in a --kernel-trace run of
+        bench.py: kernel, grid, start, duration, the FP32 table bytes the
+        launch moved and the bytes / duration rate.  The bytes come from the
+        library itself (one propagation of the same seeded workload, then
+        jt_query(JT_Q_LAST_LAUNCH_BYTES)), so this step needs the GPU.
+    python -m paper_1202_3777_amd.rocprof_summary traffic --kernel PREFIX \
+        --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N \
+        --out FILE.json
+        HBM bytes per launch of the kernels whose names start with PREFIX
+        (all dispatches of all of them averaged: the propagation's pass
+        kernels) from two counter runs (FETCH_SIZE, then WRITE_SIZE), each
+        scaled by what the same counter reads for a plain copy of N bytes
+        (the runtime's copy kernel) so that the counter's unit and coverage
+        are calibrated on this GPU.
 
 The traffic file records the sha256 of the kernel source it was measured
 on; bench.py reports the traffic only while the source is unchanged.
@@ -62,35 +66,39 @@ def stats(d):
              "total_ns": int(float(r["TotalDurationNs"])), "pct": float(r["Percentage"])} for r in rows]
 
 
-def launches(d, config, tuning=None, seed=0, kernel="jt_pass_kernel"):
-    """Rows of the last propagation's launches: (grid blocks, start us, dur us, bytes)."""
+def launches(d, config, tuning=None, seed=0, kernel="jt_pass"):
+    """Rows of the last propagation's launches: (kernel, grid blocks, start us, dur us, bytes)."""
     from paper_1202_3777_amd import jt
     from paper_1202_3777_amd.instances import make_instance
     rows = [r for r in _csv(d, "*kernel_trace.csv") if r["Kernel_Name"].startswith(kernel)]
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    plan = jt.JunctionTreePlan.from_instance(make_instance(config, seed), tuning=tuning)
-    n = plan.query(jt.JT_Q_N_LAUNCHES_FUSED)
+    inst = make_instance(config, seed)
+    tree = jt.JunctionTree.from_instance(inst, device="cuda:0", tuning=tuning)
+    tree.propagate("fused")
+    n = tree.query(jt.JT_Q_N_LAUNCHES_FUSED)
     last = rows[-n:]
     t0 = int(last[0]["Start_Timestamp"])
     out = []
     for i, r in enumerate(last):
         s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
         grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0))) // int(r.get("Workgroup_Size_X", 256) or 256)
-        out.append((grid, (s - t0) / 1e3, (e - s) / 1e3, plan.query(jt.JT_Q_FUSED_LAUNCH_BYTES, i)))
+        name = r["Kernel_Name"].split("(")[0]
+        out.append((name, grid, (s - t0) / 1e3, (e - s) / 1e3, tree.query(jt.JT_Q_LAST_LAUNCH_BYTES, i)))
     span = (int(last[-1]["End_Timestamp"]) - t0) / 1e3
     return out, span
 
 
-def _match(d, name):
-    for k, v in d.items():
-        if k.startswith(name):
-            return v
-    raise KeyError(f"kernel {name} not in counter output ({list(d)[:5]})")
+def _match(d, prefix):
+    """Values of every dispatch of the kernels whose names start with prefix."""
+    names = sorted(k for k in d if k.startswith(prefix))
+    if not names:
+        raise KeyError(f"no kernel {prefix}* in counter output ({list(d)[:5]})")
+    return names, [x for k in names for x in d[k]]
 
 
 def traffic(args):
-    fetch = _match(counter_per_dispatch(args.fetch, "FETCH_SIZE"), args.kernel)
-    write = _match(counter_per_dispatch(args.write, "WRITE_SIZE"), args.kernel)
+    names, fetch = _match(counter_per_dispatch(args.fetch, "FETCH_SIZE"), args.kernel)
+    _, write = _match(counter_per_dispatch(args.write, "WRITE_SIZE"), args.kernel)
     cf = counter_per_dispatch(args.copy_fetch, "FETCH_SIZE")
     cw = counter_per_dispatch(args.copy_write, "WRITE_SIZE")
     # the reference copy kernel (torch's device-to-device copy); other
@@ -103,12 +111,14 @@ def traffic(args):
     w_scale = args.copy_bytes / cwv          # bytes per counter unit, writes
     fb = sum(fetch) / len(fetch) * f_scale
     wb = sum(write) / len(write) * w_scale
-    out = {"kernel": args.kernel, "source_sha256": kernel_source_hash(),
+    out = {"kernel": args.kernel, "kernels": [k.split("(")[0] for k in names],
+           "source_sha256": kernel_source_hash(),
            "dispatches": [len(fetch), len(write)],
            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb,
            "copy_kernel": [cfk, cwk], "copy_bytes": args.copy_bytes,
            "copy_counter_fetch": cfv, "copy_counter_write": cwv,
-           "scale_bytes_per_unit": [f_scale, w_scale], "workload": args.workload}
+           "scale_bytes_per_unit": [f_scale, w_scale], "workload": args.workload,
+           "tuning": json.loads(args.tuning) if args.tuning else {}}
     with open(args.out, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
@@ -132,6 +142,7 @@ def main(argv=None):
     t.add_argument("--copy-write", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--workload", default="")
+    t.add_argument("--tuning", default=None, help="JSON of the shape choices the counter runs used")
     t.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
@@ -141,9 +152,9 @@ def main(argv=None):
     elif a.cmd == "launches":
         rows, span = launches(a.dir, a.config, json.loads(a.tuning) if a.tuning else None, a.seed)
         busy = 0.0
-        for i, (g, st, du, b) in enumerate(rows):
+        for i, (name, g, st, du, b) in enumerate(rows):
             busy += du
-            print(f"{i:3d} jt_pass_kernel grid {g:7d} blk start {st:8.1f} dur {du:8.1f} us "
+            print(f"{i:3d} {name:22s} grid {g:7d} blk start {st:8.1f} dur {du:8.1f} us "
                   f"{b / 2**20:9.1f} MiB {b / (du * 1e3):7.0f} GB/s")
         print(f"span {span:.1f} us, kernels busy {busy:.1f} us, gaps {span - busy:.1f} us")
     else:

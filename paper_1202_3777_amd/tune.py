@@ -17,9 +17,11 @@ import os
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "jt_kernels.hip")
 
 # Candidates around the built-in defaults (group 8K..32K entries, 1280 blocks
-# per launch): one knob moved at a time, plus two joint moves.  (Lanes are
+# per launch): one knob moved at a time, joint moves, and smaller least work
+# per block (task_min) at several block targets.  (Lanes are
 # disabled in the library, so max_lanes is not searched.)
 DEFAULT_CANDIDATES: List[Dict[str, int]] = [
     {},
@@ -36,6 +38,12 @@ DEFAULT_CANDIDATES: List[Dict[str, int]] = [
     {"group_min": 16384, "target_blocks": 2560},
     {"group_min": 4096, "target_blocks": 1024},
     {"group_min": 2048, "group_div": 512},
+    {"task_min": 1},
+    {"task_min": 1, "target_blocks": 5120},
+    {"task_min": 1, "target_blocks": 10240},
+    {"task_min": 1, "target_blocks": 20480},
+    {"task_min": 2048, "target_blocks": 10240},
+    {"task_min": 2048, "target_blocks": 20480},
 ]
 
 
@@ -85,9 +93,10 @@ def autotune(inst, n_slots: Optional[int] = None, candidates: Optional[Sequence[
 def shape_key(inst, n_slots: Optional[int] = None, device_name: str = "") -> str:
     """Shape class of a tree for the tuning cache: what the shape choices
     depend on -- the tree's topology, every table and separator size, the
-    table layouts (tiles), the slot count and the GPU -- and nothing of the
-    potentials or the evidence."""
+    table layouts (tiles), the slot count, the GPU and the pass kernels'
+    source -- and nothing of the potentials or the evidence."""
     h = hashlib.sha256()
+    h.update(open(KERNEL_SOURCE, "rb").read())
     for a in (inst.card, inst.clique_off, inst.clique_vars, inst.parent):
         h.update(a.tobytes())
     h.update(str(int(n_slots if n_slots is not None else max(1, inst.n_slots))).encode())

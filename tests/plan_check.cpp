@@ -8,7 +8,8 @@
 //     exactly the (task, slot) pairs with evidence of that slot below it;
 //   * every distribute (task, active slot) pair runs exactly once, either in
 //     a multi-slot set (only when the slot reads a shared source) or alone;
-//   * the collect sources point at the slot itself or at the shared slot.
+//   * the collect sources point at the slot itself or at the shared slot;
+//   * the per-launch byte counts add up to the propagation's.
 // Prints "OK <summary>" or "FAIL <reason>" and exits non-zero on failure.
 #include <cstdio>
 #include <cstdlib>
@@ -71,6 +72,9 @@ int main(int argc, char **argv) {
         jt::Dynamic D;
         jt::build_dynamic(P, ev, na, D);
         const int32_t N = P.n_slots;
+        int64_t lsum = 0;
+        for (int64_t b : D.launch_bytes) lsum += b;
+        if (D.launch_bytes.size() != P.fused.size() || lsum != D.bytes) return fail("launch bytes");
         std::vector<std::vector<char>> dirty(na, std::vector<char>(nc, 0));
         for (int32_t s = 0; s < na; ++s) {
             dirty[s][P.root] = 1;

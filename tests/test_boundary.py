@@ -236,7 +236,7 @@ def test_tuning_changes_cuts_not_work():
     inst = make_instance("c2", 2, n_cliques=12)
     base = jt.JunctionTreePlan.from_instance(inst)
     for tuning in ({"group_min": 4096}, {"group_max": 65536, "group_div": 256}, {"target_blocks": 300},
-                   {"max_lanes": 1}):
+                   {"max_lanes": 1}, {"task_min": 1}, {"task_min": 1, "target_blocks": 20480}):
         p = jt.JunctionTreePlan.from_instance(inst, tuning=tuning)
         for q in (jt.JT_Q_BYTES_FUSED, jt.JT_Q_BYTES_PLAIN, jt.JT_Q_ENTRIES_PER_SWEEP, jt.JT_Q_ROOT):
             assert p.query(q) == base.query(q)
@@ -244,7 +244,8 @@ def test_tuning_changes_cuts_not_work():
             assert p.query(jt.JT_Q_N_LANES) == 0
             assert p.query(jt.JT_Q_N_LAUNCHES_FUSED) == p.query(jt.JT_Q_HEIGHT) + p.query(jt.JT_Q_DEPTH)
     # lanes are disabled: asking for more than one is refused
-    for bad in ({"group_min": -1}, {"max_lanes": 9}, {"max_lanes": 2}, {"group_min": 65536, "group_max": 1024}):
+    for bad in ({"group_min": -1}, {"max_lanes": 9}, {"max_lanes": 2}, {"group_min": 65536, "group_max": 1024},
+                {"task_min": -1}):
         with pytest.raises(jt.JTError) as ei:
             jt.JunctionTreePlan.from_instance(inst, tuning=bad)
         assert ei.value.code == jt.JT_E_ARG
@@ -287,3 +288,28 @@ def test_merged_compile_structure():
     with pytest.raises(jt.JTError) as ei:
         jt.jt_compile_merged(inst.card, inst.clique_off, inst.clique_vars, bad, 4, 4096)
     assert ei.value.code == jt.JT_E_NOT_JUNCTION_TREE
+
+
+def test_algorithmic_bytes():
+    # the fused schedule's algorithmic bytes: per clique, slot and entry
+    # 12 B for a leaf, 16 B for an inner clique, 8 B for the root of the
+    # schedule (any clique of degree one other than the root is a leaf)
+    for cfg, kw in (("c1", {}), ("c2", {"n_cliques": 12}), ("c4", {"n_slots": 6})):
+        inst = make_instance(cfg, 1, **kw)
+        plan = jt.JunctionTreePlan.from_instance(inst)
+        root = plan.query(jt.JT_Q_ROOT)
+        deg = np.zeros(inst.n_cliques, int)
+        for c, p in enumerate(inst.parent):
+            if p >= 0:
+                deg[c] += 1
+                deg[p] += 1
+        size = [int(np.prod(inst.card[inst.vars_of(c)])) for c in range(inst.n_cliques)]
+        per_slot = sum(s * (8 if c == root else 12 if deg[c] == 1 else 16) for c, s in enumerate(size))
+        n = max(1, inst.n_slots)
+        assert plan.query(jt.JT_Q_ALG_BYTES, 0) == per_slot * n
+        assert plan.query(jt.JT_Q_ALG_BYTES, 1) == per_slot
+    single = jt.JunctionTreePlan(np.array([2, 3], np.int32), np.array([0, 2], np.int64), np.array([0, 1], np.int32),
+                                 np.array([-1], np.int32), 1)
+    assert single.query(jt.JT_Q_ALG_BYTES, 0) == 8 * 6
+    with pytest.raises(jt.JTError):
+        single.query(jt.JT_Q_ALG_BYTES, 2)

@@ -108,7 +108,16 @@ def test_c4_batched_slots():
     run_case(inst, modes=("fused", "graph"))
 
 
-C4_BENCH_TUNING = {"target_blocks": 5120}   # the shape the autotuner picks for this tree
+C4_FALLBACK_TUNING = {"target_blocks": 20480}
+
+
+def bench_tuning(inst):
+    """The shape choice the benchmark runs this tree with: the autotuner's
+    cached choice for this GPU and kernel source, else a fixed one."""
+    import torch
+    from paper_1202_3777_amd import tune
+    t = tune.cache_lookup(tune.shape_key(inst, device_name=torch.cuda.get_device_name(0)))
+    return t if t is not None else C4_FALLBACK_TUNING
 
 
 def test_c4_full_batch_every_slot():
@@ -118,7 +127,9 @@ def test_c4_full_batch_every_slot():
     jt = _gpu()
     inst = make_instance("c4", 0)
     plan = oracle.Plan.from_instance(inst)
-    tree = jt.JunctionTree.from_instance(inst, tuning=C4_BENCH_TUNING)
+    tuning = bench_tuning(inst)
+    print(f"[parity] c4 shape choice {tuning}")
+    tree = jt.JunctionTree.from_instance(inst, tuning=tuning)
     tree.propagate("graph")
     assert tree.query(jt.JT_Q_LAST_SHARED) == 1
     passes = tree.query(jt.JT_Q_LAST_COLLECT_PASSES)
@@ -191,6 +202,12 @@ def test_odd_shapes():
                     evidence=[([1, 3], [17, 2])]),
         from_arrays([3] * 9, [[0, 1, 2, 3, 4, 5], [5, 6, 7, 8, 0]], [-1, 0], seed=5,
                     evidence=[([6], [1])]),
+        # a clique with 12 children: gathers past the register ones, staged in LDS
+        from_arrays([2] * 30, [[0, 1, 2, 3, 4, 5]] + [[k % 6, (k + 1) % 6, 6 + 2 * k, 7 + 2 * k] for k in range(12)],
+                    [-1] + [0] * 12, seed=6, evidence=[([7, 20, 2], [1, 0, 1])]),
+        # 24 children of a 256-entry clique: too many to stage, read tile by tile
+        from_arrays([2] * 56, [list(range(8))] + [[k % 8, (k + 3) % 8, 8 + 2 * k, 9 + 2 * k] for k in range(24)],
+                    [-1] + [0] * 24, seed=7, evidence=[([9, 30, 1], [0, 1, 1])]),
     ]
     for inst in cases:
         run_case(inst)
