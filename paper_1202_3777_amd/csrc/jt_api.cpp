@@ -245,13 +245,8 @@ jt_status prepare(jt_tree t, int n_active, bool fused) {
 }
 
 // Launch flags: batched fused launches read collect data through the collect
-// sources; initial tables are streamed when a single slot reads them.
-int launch_flags(const jt::Plan &P, const jt::Launch &l, bool fused, int n_active) {
-    int f = 0;
-    if (P.share && fused) f |= JT_PF_SHARE;
-    if (n_active == 1 && !l.listed) f |= JT_PF_NT_INIT;
-    return f;
-}
+// sources.
+int launch_flags(const jt::Plan &P, bool fused) { return (P.share && fused) ? JT_PF_SHARE : 0; }
 
 // Launch list L on the bound stream and, for launches of a lane, on that
 // lane's stream: the lanes first wait for the bound stream (fork), a launch
@@ -299,7 +294,7 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
             if (l.multi)
                 e = jt_launch_pass_multi(d, l.begin, l.lds_floats, l.work_off, l.work_idx, grid, s);
             else
-                e = jt_launch_pass(d, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, l, fused, S),
+                e = jt_launch_pass(d, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, fused),
                                    l.listed ? l.work_off : -1, l.work_idx, grid, s);
         }
         if (e != hipSuccess) return hip_err(e, "kernel launch");
@@ -1091,7 +1086,7 @@ jt_status jt_profile(jt_tree t, int32_t mode, double *pass_ms, double *finalize_
                 e = jt_launch_pass_multi(t->dev, l.begin, l.lds_floats, l.work_off, l.work_idx,
                                          t->dyn.grid[l.work_idx], t->stream);
             else
-                e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, l, fused, S),
+                e = jt_launch_pass(t->dev, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, fused),
                                    l.listed ? l.work_off : -1, l.work_idx, l.listed ? t->dyn.grid[l.work_idx] : 0,
                                    t->stream);
         }

@@ -75,7 +75,6 @@ enum { JT_SRC_INIT = 0, JT_SRC_COLL = 1, JT_SRC_OUT = 2 };
 
 // Launch flags of the pass kernel.
 #define JT_PF_SHARE 1     // collect data are read through the per-slot collect sources
-#define JT_PF_NT_INIT 2   // initial tables are streamed (read by one slot only)
 enum { JT_DST_NONE = -1, JT_DST_COLL = 1, JT_DST_OUT = 2 };
 
 // One streaming pass over one clique table (per slot):
@@ -103,16 +102,8 @@ typedef struct {
     int32_t msg;                // message this pass produces and finalizes, -1 none
     int32_t wave_groups;        // 1: short groups (one kept-outer configuration each,
                                 // all its tiles), each streamed whole by one wave
-    int32_t x_lds;              // gathers past the first JT_NG_REG: float offset in the dynamic
-                                // LDS of their staged tables (JT_X_LDS_FLOATS), -1: read from
-                                // global memory tile by tile
+    int32_t pad;
 } JtItem;
-
-/* LDS the gathers past the first JT_NG_REG of an item take (x = their
- * number, T = the tile): Jin [x][T], per wave the Jout of its current 64
- * tiles [waves][x][64], and per gather its ratio location [x][2] (LDS offset
- * or -1, global offset). */
-#define JT_X_LDS_FLOATS(x, T) ((x) * (T) + JT_WAVES_PER_BLOCK * (x) * JT_WAVE + 2 * (x))
 
 // A block's share of an item: groups [g0, g1), one after the other.
 typedef struct {

@@ -112,12 +112,9 @@ __device__ __forceinline__ void fold_store(const float *row, const PassLds &L, i
     }
 }
 
-// Streaming (non-temporal) loads and stores of table entries: a table is
-// touched once per pass, so its lines need not stay in L2, and stores that
-// bypass it leave no dirty lines for the end-of-kernel write-back.
-__device__ __forceinline__ jt_f4 ld_nt4(const float *p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const jt_f4 *>(p));
-}
+// Streaming (non-temporal) stores of table entries: a table is written once
+// per pass, and stores that bypass L2 leave no dirty lines for the
+// end-of-kernel write-back.
 __device__ __forceinline__ void st_nt4(float *p, float a, float b, float c, float d) {
     const jt_f4 w = {a, b, c, d};
     __builtin_nontemporal_store(w, reinterpret_cast<jt_f4 *>(p));
@@ -127,7 +124,7 @@ __device__ __forceinline__ void st_nt4(float *p, float a, float b, float c, floa
 // NT_SRC: the source table is streamed with non-temporal loads; off when the
 // launch reads the shared initial tables for several slots (those stay cached
 // for the other slots).
-template <int VEC, bool NT_SRC, bool XG>
+template <int VEC>
 __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task, int slot,
                                            const JtGather *__restrict__ gfirst,
                                            const JtGather *__restrict__ gathers, const int32_t *__restrict__ meta,
@@ -207,28 +204,6 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     const int32_t rout_off = it.o_rout_tile;
     float *part = partial + (int64_t)slot * st.partial + it.partial_off;
 
-    // gathers past the first JT_NG_REG (cliques with many children): their
-    // Jin tables and ratio locations are staged in LDS once per block, and
-    // each wave keeps the Jout values of its current 64 tiles there, fetched
-    // lane-parallel with the chunk's metadata
-    const int nx = __builtin_amdgcn_readfirstlane(ng > JT_NG_REG ? ng - JT_NG_REG : 0);
-    const int xoff = __builtin_amdgcn_readfirstlane(it.x_lds);
-    int32_t *__restrict__ xb = XG ? reinterpret_cast<int32_t *>(lds_ratio + xoff) : nullptr;
-    auto fetch_xjo = [&](int my_o, bool live) {
-        if (!XG) return;
-        int32_t *__restrict__ xjo = xb + nx * T + wave * nx * JT_WAVE;
-        for (int x0 = 0; x0 < nx; x0 += 4) {
-            int v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                v[k] = (x0 + k < nx && live) ? meta[gathers[it.gather_base + JT_NG_REG + x0 + k].jout_off + my_o] : 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (x0 + k < nx) xjo[(x0 + k) * JT_WAVE + lane] = v[k];
-        }
-        wave_sync();
-    };
-
     // issue the loads of chunk tiles [u0, min(u0 + U, nt))
     auto issue = [&](TileBatch &B, int u0, int nt, int my_o) {
 #pragma unroll
@@ -245,24 +220,16 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                 const float *base = src + (int64_t)o * T;
                 if (VEC == 4) {
                     if (valid[0]) {
-                        if (NT_SRC) {
-                            const jt_f4 v4 = ld_nt4(base + pos[0]);
-                            B.x[u][0] = v4.x;
-                            B.x[u][1] = v4.y;
-                            B.x[u][2] = v4.z;
-                            B.x[u][3] = v4.w;
-                        } else {
-                            const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
-                            B.x[u][0] = v4.x;
-                            B.x[u][1] = v4.y;
-                            B.x[u][2] = v4.z;
-                            B.x[u][3] = v4.w;
-                        }
+                        const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
+                        B.x[u][0] = v4.x;
+                        B.x[u][1] = v4.y;
+                        B.x[u][2] = v4.z;
+                        B.x[u][3] = v4.w;
                     }
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (valid[q]) B.x[u][q] = NT_SRC ? __builtin_nontemporal_load(base + pos[q]) : base[pos[q]];
+                        if (valid[q]) B.x[u][q] = base[pos[q]];
                 }
             }
         }
@@ -290,30 +257,14 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                     }
                 }
             }
-            if (XG) {
-                // gathers past the register ones, from their LDS-staged tables
-                const int32_t *__restrict__ xjo = xb + nx * T + wave * nx * JT_WAVE;
-                const int32_t *__restrict__ xl = xb + nx * T + JT_WAVES_PER_BLOCK * nx * JT_WAVE;
-                for (int x = 0; x < nx; ++x) {
-                    const int jo = __builtin_amdgcn_readfirstlane(xjo[x * JT_WAVE + uu]);
-                    const int32_t lo = __builtin_amdgcn_readfirstlane(xl[2 * x]);
-                    const int32_t go = __builtin_amdgcn_readfirstlane(xl[2 * x + 1]);
+            for (int gg = JT_NG_REG; gg < ng; ++gg) {
+                const JtGather G = gathers[it.gather_base + gg];
+                const int jo = meta[G.jout_off + o];
+                const int32_t go = gather_off(G);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = jo + (valid[q] ? xb[x * T + pos[q]] : 0);
-                        v[q] *= lo >= 0 ? lds_ratio[lo + j] : sep[go + j];
-                    }
-                }
-            } else {
-                for (int gg = JT_NG_REG; gg < ng; ++gg) {
-                    const JtGather G = gathers[it.gather_base + gg];
-                    const int jo = meta[G.jout_off + o];
-                    const int32_t go = gather_off(G);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = jo + (valid[q] ? meta[G.jin_off + pos[q]] : 0);
-                        v[q] *= G.lds_off >= 0 ? lds_ratio[G.lds_off + j] : sep[go + j];
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const int j = jo + (valid[q] ? meta[G.jin_off + pos[q]] : 0);
+                    v[q] *= G.lds_off >= 0 ? lds_ratio[G.lds_off + j] : sep[go + j];
                 }
             }
 #pragma unroll
@@ -370,18 +321,6 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
         if (has_out) {
             for (int t = threadIdx.x; t < T; t += JT_BLOCK) L.perm[t] = meta[it.o_perm + t];
             for (int t = threadIdx.x; t < it.o_n_cls; t += JT_BLOCK) L.clsj[t] = meta[it.o_clsj + t];
-        }
-        if (XG) {
-            for (int k = threadIdx.x; k < nx * T; k += JT_BLOCK) {
-                const int x = k / T;
-                xb[k] = meta[gathers[it.gather_base + JT_NG_REG + x].jin_off + (k - x * T)];
-            }
-            if (threadIdx.x < nx) {
-                const JtGather G = gathers[it.gather_base + JT_NG_REG + threadIdx.x];
-                int32_t *__restrict__ xl = xb + nx * T + JT_WAVES_PER_BLOCK * nx * JT_WAVE + 2 * threadIdx.x;
-                xl[0] = G.lds_off;
-                xl[1] = gather_off(G);
-            }
         }
         __syncthreads();
     };
@@ -448,7 +387,6 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             int my_jo[JT_NG_REG];
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) my_jo[gg] = (gg < ngr && live) ? meta[gr[gg].jout_off + my_o] : 0;
-            fetch_xjo(my_o, live);
             issue(A, 0, nt, my_o);
             if (!staged) {
                 stage();
@@ -498,7 +436,6 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             int my_jo[JT_NG_REG];
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) my_jo[gg] = (gg < ngr && live) ? meta[gr[gg].jout_off + my_o] : 0;
-            fetch_xjo(my_o, live);
             issue(A, 0, nt, my_o);
             if (!staged) {
                 stage();
@@ -1256,38 +1193,25 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
         // source and destination tables of this slot; an absorbed collect
         // table is read from the clique's collect source
         const float *src;
-        bool shared_src;
-        if (it.src_kind == JT_SRC_INIT) {
+        if (it.src_kind == JT_SRC_INIT)
             src = init + it.src_off;
-            shared_src = !(flags & JT_PF_NT_INIT);
-        } else if (it.src_kind == JT_SRC_COLL) {
-            const int64_t cs = coll_slot(cs_row, it.clique, slot);
-            src = coll + cs * st.coll + it.src_off;
-            shared_src = cs != slot;
-        } else {
+        else if (it.src_kind == JT_SRC_COLL)
+            src = coll + coll_slot(cs_row, it.clique, slot) * st.coll + it.src_off;
+        else
             src = out + (int64_t)slot * st.out + it.src_off;
-            shared_src = false;
-        }
         float *dst = nullptr;
         if (it.dst_kind == JT_DST_COLL) dst = coll + (int64_t)slot * st.coll + it.dst_off;
         if (it.dst_kind == JT_DST_OUT) dst = out + (int64_t)slot * st.out + it.dst_off;
-        // a table read by one slot is streamed (non-temporal loads); one that
-        // several slots read stays cached for the others
-#define JT_PASS(V, NT, X)                                                                                   \
-    pass_block<V, NT, X>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale, partial, \
-                         st, lds_ratio, L)
-        if (it.x_lds >= 0) {
-            if (it.vec == 4) {
-                if (!shared_src) JT_PASS(4, true, true); else JT_PASS(4, false, true);
-            } else {
-                if (!shared_src) JT_PASS(1, true, true); else JT_PASS(1, false, true);
-            }
-        } else if (it.vec == 4) {
-            if (!shared_src) JT_PASS(4, true, false); else JT_PASS(4, false, false);
-        } else {
-            if (!shared_src) JT_PASS(1, true, false); else JT_PASS(1, false, false);
-        }
-#undef JT_PASS
+        // table entries are loaded through the caches (initial and
+        // evidence-free tables are read by many slots) and stored
+        // non-temporally; one instance per lane layout keeps the kernel's
+        // code small
+        if (it.vec == 4)
+            pass_block<4>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale,
+                          partial, st, lds_ratio, L);
+        else
+            pass_block<1>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale,
+                          partial, st, lds_ratio, L);
         if (it.msg >= 0) {
             int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
             // Hand-off to the finalizing block, ordered by the hardware:

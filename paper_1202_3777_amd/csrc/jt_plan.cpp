@@ -331,17 +331,6 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         P.gathers.push_back(G);
     }
     it.n_gather_lds = n_lds;
-    it.x_lds = -1;
-    if (it.n_gather > JT_NG_REG) {
-        // the Jin tables, per-tile Jout values and ratio locations of the
-        // gathers past the register ones, staged in LDS after the ratio tables
-        const int32_t x0 = (int32_t)align_up(lds, 4);
-        const int32_t xn = JT_X_LDS_FLOATS(it.n_gather - JT_NG_REG, C.T);
-        if (x0 + xn <= JT_LDS_RATIO_FLOATS) {
-            it.x_lds = x0;
-            lds = x0 + xn;
-        }
-    }
     it.lds_floats = lds;
     it.scale_clique = scale_clique;
     it.ev = (src_kind == JT_SRC_INIT) ? 1 : 0;
@@ -454,17 +443,6 @@ bool verify_plan(const Plan &P, std::string &why) {
         }
         if (it.gather_base < 0 || it.gather_base + it.n_gather > (int32_t)P.gathers.size()) return bad("gather range");
         if (it.n_gather_lds > it.n_gather || it.lds_floats > JT_LDS_RATIO_FLOATS) return bad("LDS budget");
-        if (it.x_lds >= 0) {
-            if (it.n_gather <= JT_NG_REG || it.x_lds % 4 != 0 ||
-                it.x_lds + (int64_t)JT_X_LDS_FLOATS(it.n_gather - JT_NG_REG, it.T) > it.lds_floats)
-                return bad("extra gather LDS range");
-            for (int32_t g = 0; g < it.n_gather; ++g) {
-                const JtGather &G = P.gathers[it.gather_base + g];
-                if (G.lds_off >= 0 && G.lds_off + G.ssize > it.x_lds) return bad("extra gathers overlap ratio tables");
-            }
-        } else if (it.x_lds != -1) {
-            return bad("extra gather LDS offset");
-        }
         for (int g = 0; g < it.n_gather; ++g) {
             const JtGather &G = P.gathers[it.gather_base + g];
             if (G.view < 0 || G.view >= (int32_t)P.views.size() || P.views[G.view].clique != it.clique) return bad("gather view");
