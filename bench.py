@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--queries", type=int, default=2000, help="serving: queries per arrival-rate run")
     ap.add_argument("--capacity", type=int, default=8, help="serving: evidence slots per resident tree")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM admission budget")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only measure this GPU's streaming ceilings (fill, read, copy, scale-in-place kernels of "
+                         "torch, 256 MiB and 2 GiB) and print them as one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB FP32 tensor 5 times (the known-size reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -119,6 +122,36 @@ def copy_ceiling_gbs(torch, nbytes=2 << 30, reps=10):
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def ceilings():
+    """HBM rates of plain streaming kernels: write-only (fill), read-only
+    (sum), read+write (copy, in-place-free scale); bytes moved / time."""
+    import torch
+    out = {}
+    for nb in (256 << 20, 2 << 30):
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+
+        def rate(fn, moved, reps=20):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return moved / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+        out[f"{nb >> 20} MiB"] = {"fill_write_gbs": rate(lambda: b.fill_(1.5), nb),
+                                  "sum_read_gbs": rate(lambda: a.sum(), nb),
+                                  "copy_gbs": rate(lambda: b.copy_(a), 2 * nb),
+                                  "scale_gbs": rate(lambda: torch.mul(a, 1.0001, out=b), 2 * nb)}
+        del a, b
+        torch.cuda.empty_cache()
+    print(json.dumps({"ceilings": out, "device": torch.cuda.get_device_name(0)}))
 
 
 def measured_traffic(cfg, kernel, tuning=None):
@@ -326,6 +359,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.ceilings:
+        ceilings()
         return
     if args.config == "c5":
         serve_main(args, torch)

@@ -18,6 +18,13 @@
         (the runtime's copy kernel) so that the counter's unit and coverage
         are calibrated on this GPU.
 
+    python -m paper_1202_3777_amd.rocprof_summary counters DIR... --launches N
+        per launch of the last propagation (the last N dispatches of the pass
+        kernels) the SQ / TCP counters of one or more --pmc runs of the same
+        command: waves, cycles per wave, the share of wave cycles spent
+        waiting and issuing VALU instructions, instructions per wave, the
+        mean L2 read and write latency seen from the L1 (cycles).
+
 The traffic file records the sha256 of the kernel source it was measured
 on; bench.py reports the traffic only while the source is unchanged.
 """
@@ -124,6 +131,22 @@ def traffic(args):
     print(json.dumps(out, indent=1))
 
 
+def counters(dirs, n_launch, kernel="jt_pass"):
+    """{launch index: {counter: value}} over the last n_launch pass dispatches."""
+    per = defaultdict(dict)
+    for d in dirs:
+        disp = defaultdict(dict)
+        for r in _csv(d, "*counter_collection.csv"):
+            if not r["Kernel_Name"].startswith(kernel):
+                continue
+            did = int(r["Dispatch_Id"])
+            disp[did][r["Counter_Name"]] = disp[did].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            disp[did]["_kernel"] = r["Kernel_Name"].split("(")[0]
+        for i, did in enumerate(sorted(disp)[-n_launch:]):
+            per[i].update(disp[did])
+    return per
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -144,6 +167,9 @@ def main(argv=None):
     t.add_argument("--workload", default="")
     t.add_argument("--tuning", default=None, help="JSON of the shape choices the counter runs used")
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--launches", type=int, required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         for r in stats(a.dir):
@@ -157,6 +183,20 @@ def main(argv=None):
             print(f"{i:3d} {name:22s} grid {g:7d} blk start {st:8.1f} dur {du:8.1f} us "
                   f"{b / 2**20:9.1f} MiB {b / (du * 1e3):7.0f} GB/s")
         print(f"span {span:.1f} us, kernels busy {busy:.1f} us, gaps {span - busy:.1f} us")
+    elif a.cmd == "counters":
+        per = counters(a.dirs, a.launches)
+        print(f"{'#':>3} {'kernel':22s} {'waves':>6} {'cyc/wave':>8} {'wait%':>6} {'valu%':>6} {'valu/w':>7} "
+              f"{'salu/w':>7} {'vmem/w':>7} {'lds/w':>6} {'rd lat':>7} {'wr lat':>7}")
+        for i in sorted(per):
+            x = per[i]
+            w = max(1.0, x.get("SQ_WAVES", 1.0))
+            wc = max(1.0, x.get("SQ_WAVE_CYCLES", 1.0))
+            rl = x.get("TCP_TCC_READ_REQ_LATENCY_sum", 0.0) / max(1.0, x.get("TCP_TCC_READ_REQ_sum", 1.0))
+            wl = x.get("TCP_TCC_WRITE_REQ_LATENCY_sum", 0.0) / max(1.0, x.get("TCP_TCC_WRITE_REQ_sum", 1.0))
+            print(f"{i:3d} {x.get('_kernel', '')[:22]:22s} {w:6.0f} {wc / w:8.0f} {100 * x.get('SQ_WAIT_ANY', 0) / wc:6.1f} "
+                  f"{100 * x.get('SQ_ACTIVE_INST_VALU', 0) / wc:6.1f} {x.get('SQ_INSTS_VALU', 0) / w:7.0f} "
+                  f"{x.get('SQ_INSTS_SALU', 0) / w:7.0f} {x.get('SQ_INSTS_VMEM', 0) / w:7.0f} "
+                  f"{x.get('SQ_INSTS_LDS', 0) / w:6.0f} {rl:7.0f} {wl:7.0f}")
     else:
         traffic(a)
 
