@@ -75,7 +75,7 @@ def parse():
                          "on: always tune (and store the choice in the cache)")
     ap.add_argument("--tuning", default=None, help="JSON of jt_tuning fields, instead of autotuning")
     ap.add_argument("--queries", type=int, default=2000, help="serving: queries per arrival-rate run")
-    ap.add_argument("--capacity", type=int, default=8, help="serving: evidence slots per resident tree")
+    ap.add_argument("--capacity", type=int, default=16, help="serving: evidence slots per lane of a resident tree")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM admission budget")
     ap.add_argument("--ceilings", action="store_true",
                     help="only measure this GPU's streaming ceilings (fill, read, copy, scale-in-place kernels of "

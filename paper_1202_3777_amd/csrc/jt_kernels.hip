@@ -1419,30 +1419,54 @@ hipError_t jt_launch_plain_init(const JtDev &d, int n_slots, hipStream_t s) {
 // of slots [slot0, slot0 + n) packed in clique order, slot after slot, and
 // their log Z (-inf when the evidence has probability zero).  Block
 // (slot, clique) copies one table, float4 at a time when both ends allow.
+// Read-out: the posteriors of slots [slot0, slot0 + n) packed in clique
+// order, slot after slot, and each slot's log Z.  Block b copies a fixed
+// chunk of one slot's packed range (blocks spread over every clique, however
+// large): it finds the first clique overlapping its chunk by binary search
+// over the packed offsets, then copies clique segment by clique segment, each
+// thread four entries per round (loads before stores).
+#define JT_RO_CHUNK 8192
 extern "C" __global__ __launch_bounds__(JT_BLOCK) void jt_read_out_kernel(
     const float *__restrict__ out, int64_t out_stride, const int64_t *__restrict__ cltab, int n_cliques,
-    int slot0, int64_t packed_total, const double *__restrict__ lam, int64_t lam_stride,
+    int slot0, int64_t packed_total, int n_chunks, const double *__restrict__ lam, int64_t lam_stride,
     const int32_t *__restrict__ flag, float *__restrict__ dst, double *__restrict__ log_z) {
-    const int k = blockIdx.x / n_cliques, c = blockIdx.x - k * n_cliques;
+    const int k = blockIdx.x / n_chunks, ch = blockIdx.x - k * n_chunks;
     const int slot = slot0 + k;
-    const int64_t off = cltab[3 * c], n = cltab[3 * c + 1], po = cltab[3 * c + 2];
-    const float *__restrict__ a = out + (int64_t)slot * out_stride + off;
-    float *__restrict__ b = dst + (int64_t)k * packed_total + po;
-    if ((reinterpret_cast<uintptr_t>(b) & 15) == 0 && (n & 3) == 0) {
-        const float4 *__restrict__ a4 = reinterpret_cast<const float4 *>(a);
-        float4 *__restrict__ b4 = reinterpret_cast<float4 *>(b);
-        for (int64_t i = threadIdx.x; i < n / 4; i += JT_BLOCK) b4[i] = a4[i];
-    } else {
-        for (int64_t i = threadIdx.x; i < n; i += JT_BLOCK) b[i] = a[i];
-    }
-    if (c == 0 && threadIdx.x == 0)
+    const int64_t i0 = (int64_t)ch * JT_RO_CHUNK;
+    const int64_t i1 = min(packed_total, i0 + (int64_t)JT_RO_CHUNK);
+    if (ch == 0 && threadIdx.x == 0)
         log_z[k] = flag[slot] ? -INFINITY : lam[(int64_t)slot * lam_stride + JT_LAM_LOGZ(n_cliques)];
+    // last clique whose packed offset is <= i0 (offsets ascend with the clique)
+    int lo = 0, hi = n_cliques - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cltab[3 * mid + 2] <= i0) lo = mid;
+        else hi = mid - 1;
+    }
+    const float *__restrict__ src = out + (int64_t)slot * out_stride;
+    float *__restrict__ b = dst + (int64_t)k * packed_total;
+    for (int c = lo; c < n_cliques; ++c) {
+        const int64_t off = cltab[3 * c], n = cltab[3 * c + 1], po = cltab[3 * c + 2];
+        if (po >= i1) break;
+        const int64_t j0 = max(i0, po), j1 = min(i1, po + n);
+        const int64_t shift = off - po;   // packed entry j of this clique is src[j + shift]
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += 4 * JT_BLOCK) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = j + u * JT_BLOCK < j1 ? src[j + u * JT_BLOCK + shift] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j + u * JT_BLOCK < j1) b[j + u * JT_BLOCK] = v[u];
+        }
+    }
 }
 
 hipError_t jt_launch_read_out(const JtDev &d, int slot0, int n_slots, int64_t packed_total, float *dst,
                               double *log_z, hipStream_t s) {
-    hipLaunchKernelGGL(jt_read_out_kernel, dim3((unsigned)(n_slots * d.n_cliques)), dim3(JT_BLOCK), 0, s, d.out,
-                       d.out_stride, d.cltab, d.n_cliques, slot0, packed_total, d.lam, d.lam_stride, d.flag, dst,
-                       log_z);
+    const int64_t n_chunks = std::max<int64_t>(1, (packed_total + JT_RO_CHUNK - 1) / JT_RO_CHUNK);
+    if (n_chunks * n_slots > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(jt_read_out_kernel, dim3((unsigned)(n_slots * n_chunks)), dim3(JT_BLOCK), 0, s, d.out,
+                       d.out_stride, d.cltab, d.n_cliques, slot0, packed_total, (int)n_chunks, d.lam, d.lam_stride,
+                       d.flag, dst, log_z);
     return hipGetLastError();
 }

@@ -10,12 +10,14 @@ batches at once.  Queries arrive over time; the loop
      batch's posteriors have been read out into per-query device buffers)
      and hands each result to ``on_done``;
   2. admits waiting queries in arrival order while the device memory their
-     results need (one packed posterior buffer each, allocated at
-     admission and held until the result is handed over) fits the budget
-     beside the resident trees; a query whose tree already has a full queue
-     is skipped for now, so queries for other trees do not wait behind it;
+     results need (one packed posterior buffer each, reserved at admission,
+     allocated on the lane's stream when the batch launches, held until the
+     result is handed over) fits the budget beside the resident trees; a
+     query whose tree already has a full queue is skipped for now, so
+     queries for other trees do not wait behind it;
   3. launches, for every tree with admitted queries and an idle lane, one
-     propagation over up to ``capacity`` of them, packed into slots 0..k-1.
+     propagation over up to ``capacity`` of them, packed into slots 0..k-1,
+     and one read-out of their posteriors.
 
 Batches of different trees, and of the same tree on different lanes, run
 concurrently on their own streams, so work of queries that arrived at
@@ -101,31 +103,30 @@ class TreeExecutor:
                 l.tree.propagate(self.mode, n_active=k)
 
     def alloc_result(self, q: Query, lane: Optional[int] = None):
-        """The query's read-out buffers (posteriors, log Z) on the device."""
-        torch = self.torch
-        post = torch.empty(self.total_entries, dtype=torch.float32, device=self.device)
-        lz = torch.empty(1, dtype=torch.float64, device=self.device)
-        return post, lz
+        """Nothing at admission (the budget reserves the bytes): a batch's
+        result buffers are allocated when it launches, on its lane's stream."""
+        return None
 
     def launch(self, queries: Sequence[Query], lane: int):
-        """Propagate `queries` in slots 0..k-1 of `lane`, read each result out
-        into its own buffers, and return an event recorded after that."""
+        """Propagate `queries` in slots 0..k-1 of `lane`, read their results
+        out (one device read-out for the batch, into one buffer allocated on
+        the lane's stream, each query keeping its own part of it), and return
+        an event recorded after that."""
         L = self.lanes[lane]
         torch = self.torch
-        for k, q in enumerate(queries):
-            L.tree.set_evidence(k, q.ev_vars, q.ev_states)
-        L.tree.propagate(self.mode, n_active=len(queries))
+        k = len(queries)
+        for i, q in enumerate(queries):
+            L.tree.set_evidence(i, q.ev_vars, q.ev_states)
+        L.tree.propagate(self.mode, n_active=k)
         bytes_moved = L.tree.query(self.jt.JT_Q_BYTES_LAST)
-        for k, q in enumerate(queries):
-            post, lz = q.result
-            # the buffers were allocated on the loop's stream: the lane's
-            # stream waits for that before writing them, and the caching
-            # allocator is told they are used on the lane's stream
-            L.stream.wait_stream(torch.cuda.current_stream(torch.device(self.device)))
-            post.record_stream(L.stream)
-            lz.record_stream(L.stream)
-            self.jt.jt_read_out(L.tree.handle, k, 1, post.data_ptr(), lz.data_ptr())
-            bytes_moved += 2 * 4 * self.total_entries
+        n = self.total_entries
+        with torch.cuda.stream(L.stream):
+            post = torch.empty(k * n, dtype=torch.float32, device=self.device)
+            lz = torch.empty(k, dtype=torch.float64, device=self.device)
+        self.jt.jt_read_out(L.tree.handle, 0, k, post.data_ptr(), lz.data_ptr())
+        for i, q in enumerate(queries):
+            q.result = (post[i * n:(i + 1) * n], lz[i:i + 1])
+        bytes_moved += 2 * 4 * n * k
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(L.stream)
         return ev, bytes_moved
