@@ -275,6 +275,13 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
     };
     hipError_t e = lanes ? fork() : hipSuccess;
     if (e != hipSuccess) return hip_err(e, "lane fork");
+    // A level's multi-slot and one-slot distribute launches touch disjoint
+    // (task, slot) pairs and read the same finished messages, so the
+    // multi-slot one runs on the side stream (forked from the bound stream
+    // by an event) while the one-slot one runs on the bound stream, which
+    // then waits for the side stream's join event: each fills the other's
+    // ramp and tail.  Inside a captured graph these are two parallel nodes.
+    bool pending_join = false;
     for (const jt::Launch &l : L) {
         if (l.join_before && lanes) {
             e = join();
@@ -291,11 +298,22 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
                 grid = (*grids)[l.work_idx];
                 if (grid < 1 || grid > l.work_cap) return set_err(JT_E_STATE, "listed grid out of range");
             }
-            if (l.multi)
+            if (l.multi && t->side && s == stream) {
+                e = hipEventRecord(t->side_fork, stream);
+                if (e == hipSuccess) e = hipStreamWaitEvent(t->side, t->side_fork, 0);
+                if (e == hipSuccess)
+                    e = jt_launch_pass_multi(d, l.begin, l.lds_floats, l.work_off, l.work_idx, grid, t->side);
+                if (e == hipSuccess) e = hipEventRecord(t->side_join, t->side);
+                pending_join = e == hipSuccess;
+            } else if (l.multi)
                 e = jt_launch_pass_multi(d, l.begin, l.lds_floats, l.work_off, l.work_idx, grid, s);
             else
                 e = jt_launch_pass(d, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, fused),
                                    l.listed ? l.work_off : -1, l.work_idx, grid, s);
+        }
+        if (e == hipSuccess && pending_join && !l.multi) {
+            e = hipStreamWaitEvent(stream, t->side_join, 0);
+            pending_join = false;
         }
         if (e != hipSuccess) return hip_err(e, "kernel launch");
         if (l.fork_after && lanes) {
@@ -334,6 +352,11 @@ void drop_lanes(jt_tree t) {
     for (hipEvent_t e : t->lane_done)
         if (e) (void)hipEventDestroy(e);
     if (t->fork_ev) (void)hipEventDestroy(t->fork_ev);
+    if (t->side) (void)hipStreamDestroy(t->side);
+    if (t->side_fork) (void)hipEventDestroy(t->side_fork);
+    if (t->side_join) (void)hipEventDestroy(t->side_join);
+    t->side = nullptr;
+    t->side_fork = t->side_join = nullptr;
     t->lane_stream.clear();
     t->lane_done.clear();
     t->fork_ev = nullptr;
@@ -578,6 +601,16 @@ jt_status bind_common(jt_tree t, void *workspace, size_t bytes, const float *ini
     drop_graph(t);
     drop_lanes(t);
     drop_staging(t->stage);
+    if (P.share) {
+        // default priority, like every stream here
+        hipError_t se = hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking);
+        if (se == hipSuccess) se = hipEventCreateWithFlags(&t->side_fork, hipEventDisableTiming);
+        if (se == hipSuccess) se = hipEventCreateWithFlags(&t->side_join, hipEventDisableTiming);
+        if (se != hipSuccess) {
+            drop_lanes(t);
+            return hip_err(se, "side stream");
+        }
+    }
     if (P.n_lanes > 0) {
         hipError_t le = hipEventCreateWithFlags(&t->fork_ev, hipEventDisableTiming);
         for (int32_t k = 0; k < P.n_lanes && le == hipSuccess; ++k) {

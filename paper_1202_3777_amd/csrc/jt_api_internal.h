@@ -56,6 +56,10 @@ struct jt_tree_s {
     std::vector<hipStream_t> lane_stream;
     std::vector<hipEvent_t> lane_done;
     hipEvent_t fork_ev = nullptr;
+    // batched trees: a level's multi-slot launch runs on `side`, beside the
+    // level's one-slot launch on the bound stream (fork and join by events)
+    hipStream_t side = nullptr;
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
     int last_mode = -1;
     int last_n_active = 0;
     // Bayesian-network trees: the compiled network (cliques, families)
