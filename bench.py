@@ -76,6 +76,12 @@ def parse():
     ap.add_argument("--tuning", default=None, help="JSON of jt_tuning fields, instead of autotuning")
     ap.add_argument("--queries", type=int, default=2000, help="serving: queries per arrival-rate run")
     ap.add_argument("--capacity", type=int, default=16, help="serving: evidence slots per lane of a resident tree")
+    ap.add_argument("--serve-lanes", type=int, default=1,
+                    help="serving: handles (workspace + stream) per resident tree; the GPU has few hardware queues, "
+                         "and more streams queue batches of small trees behind those of large ones")
+    ap.add_argument("--serve-mode", default="fused", choices=["fused", "graph"],
+                    help="serving: schedule of the batched propagations (fused launches by default: every batch "
+                         "has new evidence, so its listed launches' grids change and a graph would be re-captured)")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM admission budget")
     ap.add_argument("--ceilings", action="store_true",
                     help="only measure this GPU's streaming ceilings (fill, read, copy, scale-in-place kernels of "
@@ -246,7 +252,7 @@ def serving_leg(args, torch):
         st["table_bytes"] = int(srv.table_bytes)
         return st
 
-    ex = make_exec(args.capacity, args.mode if args.mode != "plain" else "graph", 2)
+    ex = make_exec(args.capacity, args.serve_mode, args.serve_lanes)
     warm(ex)
     sat = run(ex, None, args.queries, args.seed + 1)
     log(f"[serve] saturated: {sat}")
@@ -270,8 +276,8 @@ def serving_leg(args, torch):
         log(f"[serve] one-query-at-a-time at the batched {frac} x rate: {plain_lat[str(frac)]}")
     del pl
     torch.cuda.empty_cache()
-    out = {"workload": "c5: " + WORKLOADS["c5"], "slots_per_tree": args.capacity, "lanes_per_tree": 2,
-           "budget_gib": args.budget_gib, "schedule": args.mode, "saturated": sat, "latency": lat,
+    out = {"workload": "c5: " + WORKLOADS["c5"], "slots_per_tree": args.capacity, "lanes_per_tree": args.serve_lanes,
+           "budget_gib": args.budget_gib, "schedule": args.serve_mode, "saturated": sat, "latency": lat,
            "roofline": {"bound": "hbm", "achieved": served_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": served_gbs / HBM_PEAK_GBS,
                         "what": "FP32 table bytes of every served propagation (shared tables once per launch) "

@@ -1046,14 +1046,16 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
             break;
         case JT_Q_FUSED_LAUNCH_KIND:
         case JT_Q_FUSED_LAUNCH_LANE:
+        case JT_Q_FUSED_LAUNCH_MULTI:
         case JT_Q_FUSED_LAUNCH_BYTES: {
             std::vector<const jt::Launch *> live;
             for (const jt::Launch &l : P.fused)
                 if (l.count > 0) live.push_back(&l);
             if (arg < 0 || arg >= (int64_t)live.size()) return set_err(JT_E_ARG, "launch index out of range");
-            *out = what == JT_Q_FUSED_LAUNCH_KIND   ? live[arg]->is_pass
-                   : what == JT_Q_FUSED_LAUNCH_LANE ? live[arg]->lane
-                                                    : live[arg]->bytes;
+            *out = what == JT_Q_FUSED_LAUNCH_KIND    ? live[arg]->is_pass
+                   : what == JT_Q_FUSED_LAUNCH_LANE  ? live[arg]->lane
+                   : what == JT_Q_FUSED_LAUNCH_MULTI ? live[arg]->multi
+                                                     : live[arg]->bytes;
             break;
         }
         case JT_Q_BYTES_LAST:

@@ -85,13 +85,22 @@ def launches(d, config, tuning=None, seed=0, kernel="jt_pass"):
     n = tree.query(jt.JT_Q_N_LAUNCHES_FUSED)
     last = rows[-n:]
     t0 = int(last[0]["Start_Timestamp"])
+    # a level's multi-slot launch runs beside its one-slot launch, so the two
+    # may start in either order: match trace rows to launches by kernel
+    multi = [tree.query(jt.JT_Q_FUSED_LAUNCH_MULTI, i) for i in range(n)]
+    byname = {True: [r for r in last if "multi" in r["Kernel_Name"]],
+              False: [r for r in last if "multi" not in r["Kernel_Name"]]}
+    used = {True: 0, False: 0}
     out = []
-    for i, r in enumerate(last):
+    for i in range(n):
+        m = bool(multi[i])
+        r = byname[m][used[m]]
+        used[m] += 1
         s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
         grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0))) // int(r.get("Workgroup_Size_X", 256) or 256)
         name = r["Kernel_Name"].split("(")[0]
         out.append((name, grid, (s - t0) / 1e3, (e - s) / 1e3, tree.query(jt.JT_Q_LAST_LAUNCH_BYTES, i)))
-    span = (int(last[-1]["End_Timestamp"]) - t0) / 1e3
+    span = (max(int(r["End_Timestamp"]) for r in last) - t0) / 1e3
     return out, span
 
 
@@ -182,7 +191,7 @@ def main(argv=None):
             busy += du
             print(f"{i:3d} {name:22s} grid {g:7d} blk start {st:8.1f} dur {du:8.1f} us "
                   f"{b / 2**20:9.1f} MiB {b / (du * 1e3):7.0f} GB/s")
-        print(f"span {span:.1f} us, kernels busy {busy:.1f} us, gaps {span - busy:.1f} us")
+        print(f"span {span:.1f} us, kernels busy {busy:.1f} us (launches of one level overlap)")
     elif a.cmd == "counters":
         per = counters(a.dirs, a.launches)
         print(f"{'#':>3} {'kernel':22s} {'waves':>6} {'cyc/wave':>8} {'wait%':>6} {'valu%':>6} {'valu/w':>7} "
