@@ -316,7 +316,8 @@ def serve_main(args, torch):
         "warmup": args.capacity, "ms_per_step": 1e3 / sat["queries_per_s"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded generator, no dataset)",
         "config": {"workload": res["workload"], "seed": args.seed, "slots_per_tree": args.capacity,
-                   "budget_gib": args.budget_gib, "schedule": args.mode, "parallelism": "single GPU"},
+                   "lanes_per_tree": args.serve_lanes, "budget_gib": args.budget_gib, "schedule": args.serve_mode,
+                   "parallelism": "single GPU"},
         "saturated": sat, "latency": res["latency"], "roofline": res["roofline"],
         "plain_one_at_a_time": res["plain_one_at_a_time"], "cpu_baseline": cpu,
     }
