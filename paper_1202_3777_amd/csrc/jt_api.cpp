@@ -278,14 +278,36 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
     // A level's multi-slot and one-slot distribute launches touch disjoint
     // (task, slot) pairs and read the same finished messages, so the
     // multi-slot one runs on the side stream (forked from the bound stream
-    // by an event) while the one-slot one runs on the bound stream, which
-    // then waits for the side stream's join event: each fills the other's
-    // ramp and tail.  Inside a captured graph these are two parallel nodes.
+    // by an event, i.e. after every earlier one-slot launch) while the
+    // one-slot one runs on the bound stream.  A one-slot pair has evidence
+    // below its clique, so its parent pass ran one-slot as well: the bound
+    // stream goes on to the next level without waiting for the side stream,
+    // except before a launch marked after_multi and at the end of the list
+    // (join event).  Inside a captured graph these are parallel branches;
+    // the one-slot launch is enqueued first, so that in the graph it is the
+    // first child of the previous level's one-slot node (the runtime keeps a
+    // node's first child on that node's stream) and the multi-slot nodes
+    // form the branch.
     bool pending_join = false;
+    const jt::Launch *deferred = nullptr;   // multi-slot launch waiting for its level's one-slot launch
+    int deferred_grid = 0;
+    auto launch_deferred = [&]() -> hipError_t {
+        const jt::Launch &m = *deferred;
+        deferred = nullptr;
+        hipError_t r = jt_launch_pass_multi(d, m.begin, m.lds_floats, m.work_off, m.work_idx, deferred_grid, t->side);
+        if (r == hipSuccess) r = hipEventRecord(t->side_join, t->side);
+        pending_join = r == hipSuccess;
+        return r;
+    };
     for (const jt::Launch &l : L) {
         if (l.join_before && lanes) {
             e = join();
             if (e != hipSuccess) return hip_err(e, "lane join");
+        }
+        if (pending_join && !l.multi && (l.after_multi || l.collect || l.is_pass != 1)) {
+            e = hipStreamWaitEvent(stream, t->side_join, 0);
+            pending_join = false;
+            if (e != hipSuccess) return hip_err(e, "side stream join");
         }
         hipStream_t s = l.lane >= 0 ? t->lane_stream[l.lane] : stream;
         if (l.is_pass == 2) {
@@ -299,27 +321,33 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
                 if (grid < 1 || grid > l.work_cap) return set_err(JT_E_STATE, "listed grid out of range");
             }
             if (l.multi && t->side && s == stream) {
-                e = hipEventRecord(t->side_fork, stream);
+                // forked here (after every earlier one-slot launch), launched
+                // after the level's one-slot launch has been enqueued
+                if (deferred) e = launch_deferred();
+                if (e == hipSuccess) e = hipEventRecord(t->side_fork, stream);
                 if (e == hipSuccess) e = hipStreamWaitEvent(t->side, t->side_fork, 0);
-                if (e == hipSuccess)
-                    e = jt_launch_pass_multi(d, l.begin, l.lds_floats, l.work_off, l.work_idx, grid, t->side);
-                if (e == hipSuccess) e = hipEventRecord(t->side_join, t->side);
-                pending_join = e == hipSuccess;
+                deferred = &l;
+                deferred_grid = grid;
             } else if (l.multi)
                 e = jt_launch_pass_multi(d, l.begin, l.lds_floats, l.work_off, l.work_idx, grid, s);
             else
                 e = jt_launch_pass(d, l.begin, l.count, S, l.lds_floats, launch_flags(t->plan, fused),
                                    l.listed ? l.work_off : -1, l.work_idx, grid, s);
         }
-        if (e == hipSuccess && pending_join && !l.multi) {
-            e = hipStreamWaitEvent(stream, t->side_join, 0);
-            pending_join = false;
-        }
+        if (e == hipSuccess && deferred && !l.multi) e = launch_deferred();
         if (e != hipSuccess) return hip_err(e, "kernel launch");
         if (l.fork_after && lanes) {
             e = fork();
             if (e != hipSuccess) return hip_err(e, "lane fork");
         }
+    }
+    if (deferred) {
+        e = launch_deferred();
+        if (e != hipSuccess) return hip_err(e, "kernel launch");
+    }
+    if (pending_join) {
+        e = hipStreamWaitEvent(stream, t->side_join, 0);
+        if (e != hipSuccess) return hip_err(e, "side stream join");
     }
     if (lanes) {
         e = join();

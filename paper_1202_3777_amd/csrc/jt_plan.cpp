@@ -516,6 +516,9 @@ bool verify_plan(const Plan &P, std::string &why) {
                                         : 8 * (int64_t)l.count * (l.collect ? P.n_regions : P.n_slots);
             if (l.work_off != wt || l.work_cap != cap || l.work_idx != nl || (l.multi && l.collect))
                 return bad("listed launch layout");
+            if (!l.collect && !l.multi && !l.after_multi)
+                for (int32_t t = l.begin; t < l.begin + l.count; ++t)
+                    if (!P.item_multi[P.tasks[t].item]) return bad("one-slot launch not ordered after multi-slot launches");
             if (l.multi) {
                 if (l.chunk_off != ct || l.chunk_cap < 1) return bad("chunk layout");
                 ct += l.chunk_cap;
@@ -1073,6 +1076,9 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err, cons
         }
         P.fused = L2;
         for (Launch &l : P.fused) {
+            if (!l.collect && !l.multi)
+                for (int32_t t = l.begin; t < l.begin + l.count; ++t)
+                    if (!P.item_multi[P.tasks[t].item]) l.after_multi = 1;
             if (!l.listed) continue;
             l.work_off = P.work_total;
             l.work_idx = P.n_listed++;

@@ -61,6 +61,12 @@ struct Launch {
     int32_t multi = 0;      // 1: multi-slot distribute launch (entries index JtChunk sets)
     int64_t chunk_off = 0;  // its first chunk in the chunk region
     int32_t chunk_cap = 0;
+    // One-slot distribute launch that may read what an earlier multi-slot
+    // launch wrote: it holds an item a multi-slot launch cannot take, so a
+    // slot whose parent pass ran in a multi-slot set can land here.  Without
+    // the flag every pair it runs has evidence below its clique, and so has
+    // the pair's parent pass, which then ran in a one-slot launch too.
+    int32_t after_multi = 0;
 };
 
 // A family (variable and parents) to be mapped into a clique: the index of

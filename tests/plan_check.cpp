@@ -157,6 +157,31 @@ int main(int argc, char **argv) {
                     if (cover[{t, s}] != 1) return fail("distribute pair coverage");
             if ((int64_t)cover.size() != (int64_t)l.count * na) return fail("distribute extra pairs");
         }
+        // a one-slot distribute launch not marked after_multi runs before the
+        // side stream's multi-slot launches are joined: none of its pairs may
+        // have its parent pass in a multi-slot set
+        std::set<std::pair<int32_t, int32_t>> multi_pair;   // (clique, slot)
+        for (const jt::Launch &l : P.fused) {
+            if (!l.listed || !l.multi) continue;
+            for (int32_t e = 0; e < D.count[l.work_idx]; ++e) {
+                const JtWork w = D.work[l.work_off + e];
+                if (w.task < 0) continue;
+                const int32_t c = P.items[P.tasks[l.begin + w.task].item].clique;
+                for (int kk = 0; kk < JT_MS; ++kk)
+                    if (D.chunks[w.slot].s[kk] >= 0) multi_pair.insert({c, D.chunks[w.slot].s[kk]});
+            }
+        }
+        for (const jt::Launch &l : P.fused) {
+            if (!l.listed || l.collect || l.multi || l.after_multi) continue;
+            for (int32_t e = 0; e < D.count[l.work_idx]; ++e) {
+                const JtWork w = D.work[l.work_off + e];
+                if (w.task < 0) continue;
+                const int32_t c = P.items[P.tasks[l.begin + w.task].item].clique;
+                const int32_t p = P.iparent[c];
+                if (p >= 0 && multi_pair.count({p, w.slot})) return fail("one-slot pass after a multi-slot parent pass, unjoined");
+                if (D.shared && p >= 0 && !dirty[w.slot][c]) return fail("one-slot pass without evidence below, unjoined");
+            }
+        }
     }
     std::printf("OK multi_sets=%lld multi_pairs=%lld single=%lld\n", n_multi_sets, n_multi_pairs, n_single);
     return 0;
