@@ -40,6 +40,26 @@ typedef float jt_f4 __attribute__((ext_vector_type(4)));
 // agent-coherent loads -- no L2 write-back or invalidate is needed.
 __device__ __forceinline__ void wait_vm_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Staging copies into LDS with global->LDS loads: the data does not pass
+// through registers, so every load of a staging step is in flight at once and
+// the block waits once (vmcnt(0), then the barrier) instead of once per round
+// of 256 entries.  One instruction moves 64 lanes' data to consecutive LDS
+// addresses from the (wave-uniform) destination.
+//  lds_copy_f4: n floats, 16 B per lane (256 per instruction); the source is
+//    16-byte aligned and readable up to n rounded up to a multiple of 4, and so
+//    is the LDS slot (the last lane may copy up to three floats of padding).
+//  lds_copy_i1: n int32, 4 B per lane (64 per instruction), exact.
+// Instruction c goes to wave (c + rot) mod 4, so small tables staged together
+// are spread over the waves.
+__device__ __forceinline__ void lds_copy_f4(const float *src, float *dst, int n, int wave, int lane, int rot) {
+    for (int c = (wave - rot) & (JT_WAVES_PER_BLOCK - 1); c * 256 < n; c += JT_WAVES_PER_BLOCK)
+        if (c * 256 + 4 * lane < n) __builtin_amdgcn_global_load_lds(src + c * 256 + 4 * lane, dst + c * 256, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_copy_i1(const int32_t *src, int32_t *dst, int n, int wave, int lane, int rot) {
+    for (int c = (wave - rot) & (JT_WAVES_PER_BLOCK - 1); c * 64 < n; c += JT_WAVES_PER_BLOCK)
+        if (c * 64 + lane < n) __builtin_amdgcn_global_load_lds(src + c * 64 + lane, dst + c * 64, 4, 0, 0);
+}
+
 // Agent-coherent load of a value written by another block of the same launch.
 __device__ __forceinline__ float ldp(const float *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -293,35 +313,24 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     };
 
     // LDS staging (ratio tables, the output view's class tables); every wave
-    // calls it once, after its first chunk's tile loads are in flight
+    // calls it once, after its first chunk's tile loads are in flight.  The
+    // ratio tables sit 16-byte aligned in the separator region (padded to 64
+    // floats) and in LDS (slots rounded up to 4 floats).
     auto stage = [&]() {
-        // the first JT_NG_REG tables: per round of 256 entries, every table's
-        // load is issued before any is stored (one memory round trip, not one
-        // per table); tables beyond them one after the other
         const int ngl = it.n_gather_lds;
-        int jmax = 0;
 #pragma unroll
         for (int g = 0; g < JT_NG_REG; ++g)
-            if (g < ngl && g < ngr) jmax = max(jmax, (int)gfirst[g].ssize);
-        for (int j0 = 0; j0 < jmax; j0 += JT_BLOCK) {
-            const int j = j0 + threadIdx.x;
-            float r[JT_NG_REG];
-#pragma unroll
-            for (int g = 0; g < JT_NG_REG; ++g)
-                r[g] = (g < ngl && g < ngr && j < gfirst[g].ssize) ? sep[gglob[g] + j] : 0.f;
-#pragma unroll
-            for (int g = 0; g < JT_NG_REG; ++g)
-                if (g < ngl && g < ngr && j < gfirst[g].ssize) lds_ratio[gfirst[g].lds_off + j] = r[g];
-        }
+            if (g < ngl && g < ngr)
+                lds_copy_f4(sep + gglob[g], lds_ratio + gfirst[g].lds_off, gfirst[g].ssize, wave, lane, g);
         for (int gg = JT_NG_REG; gg < ngl; ++gg) {
             const JtGather G = gathers[it.gather_base + gg];
-            const float *__restrict__ gt = sep + gather_off(G);
-            for (int j = threadIdx.x; j < G.ssize; j += JT_BLOCK) lds_ratio[G.lds_off + j] = gt[j];
+            lds_copy_f4(sep + gather_off(G), lds_ratio + G.lds_off, G.ssize, wave, lane, gg);
         }
         if (has_out) {
-            for (int t = threadIdx.x; t < T; t += JT_BLOCK) L.perm[t] = meta[it.o_perm + t];
-            for (int t = threadIdx.x; t < it.o_n_cls; t += JT_BLOCK) L.clsj[t] = meta[it.o_clsj + t];
+            lds_copy_i1(meta + it.o_perm, L.perm, T, wave, lane, 0);
+            lds_copy_i1(meta + it.o_clsj, L.clsj, it.o_n_cls, wave, lane, 2);
         }
+        wait_vm_stores();   // this wave's loads into LDS have landed
         __syncthreads();
     };
     TileBatch A, B;
@@ -565,22 +574,17 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
         }
     };
     auto stage = [&]() {
-        // every slot's ratio table: all loads of a round issued before any
-        // is stored (one memory round trip per 256 entries, not per slot)
-        for (int j0 = 0; j0 < G.ssize; j0 += JT_BLOCK) {
-            const int j = j0 + threadIdx.x;
-            float r[JT_MS];
+        // every slot's ratio table (16-byte aligned in the separator region
+        // and, at k * ldsz, in LDS), then the output view's class tables
 #pragma unroll
-            for (int k = 0; k < JT_MS; ++k)
-                r[k] = (k < ns && j < G.ssize) ? sep[(int64_t)ms_slot[k] * st.sep + G.sep_off + j] : 0.f;
-#pragma unroll
-            for (int k = 0; k < JT_MS; ++k)
-                if (k < ns && j < G.ssize) lds_ratio[k * ldsz + j] = r[k];
-        }
+        for (int k = 0; k < JT_MS; ++k)
+            if (k < ns)
+                lds_copy_f4(sep + (int64_t)ms_slot[k] * st.sep + G.sep_off, lds_ratio + k * ldsz, G.ssize, wave, lane, k);
         if (has_out) {
-            for (int t = threadIdx.x; t < T; t += JT_BLOCK) L.perm[t] = meta[it.o_perm + t];
-            for (int t = threadIdx.x; t < it.o_n_cls; t += JT_BLOCK) L.clsj[t] = meta[it.o_clsj + t];
+            lds_copy_i1(meta + it.o_perm, L.perm, T, wave, lane, 0);
+            lds_copy_i1(meta + it.o_clsj, L.clsj, it.o_n_cls, wave, lane, 2);
         }
+        wait_vm_stores();   // this wave's loads into LDS have landed
         __syncthreads();
     };
     TileBatch A, B;

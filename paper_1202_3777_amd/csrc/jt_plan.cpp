@@ -320,9 +320,12 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         // that sent it (the edge's other end); a distribute ratio belongs to
         // the launch's slot
         G.src_clique = g.dist ? -1 : (c == g.edge ? P.parent[g.edge] : g.edge);
-        if (lds_open && lds + E.ssize <= JT_LDS_RATIO_FLOATS) {
+        // LDS slots start 16-byte aligned: the kernels stage a table with
+        // 16-byte global->LDS loads, whose last lane may fill up to three
+        // floats of the slot's padding
+        if (lds_open && lds + align_up(E.ssize, 4) <= JT_LDS_RATIO_FLOATS) {
             G.lds_off = lds;
-            lds += (int32_t)E.ssize;
+            lds += (int32_t)align_up(E.ssize, 4);
             ++n_lds;
         } else {
             lds_open = false;
@@ -452,7 +455,8 @@ bool verify_plan(const Plan &P, std::string &why) {
             if (G.sep_off < 0 || G.sep_off + (int64_t)G.ssize > P.sep_stride) return bad("gather separator range");
             if ((g < it.n_gather_lds) != (G.lds_off >= 0)) return bad("gather LDS order");
             if (G.src_clique < -1 || G.src_clique >= P.n_cliques) return bad("gather source clique");
-            if (G.lds_off >= 0 && G.lds_off + G.ssize > it.lds_floats) return bad("gather LDS range");
+            if (G.lds_off >= 0 && (G.lds_off % 4 != 0 || G.lds_off + align_up(G.ssize, 4) > it.lds_floats))
+                return bad("gather LDS range");
         }
         if (it.scale_clique >= P.n_cliques) return bad("scale clique");
         if (it.tpg < 1 || it.nsplit < 1 || it.n_groups < 1) return bad("grouping");
