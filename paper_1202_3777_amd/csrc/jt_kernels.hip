@@ -801,9 +801,6 @@ __device__ __forceinline__ double column_sums(const float *P, float *stage, int 
 // reads) are issued first; steps 1 and 3 each issue their loads in batches
 // before using them, so the finalize costs a few memory round trips.
 // Log-scales a finalize combines (written by earlier launches).
-#ifndef JT_FS_EARLY
-#define JT_FS_EARLY 0   // 1: every block loads them at its start
-#endif
 struct FinScalars {
     double lc;           // sum of the children's collect log-scales (collect, total)
     double l0, l1, l2;   // distribute: log Z, collect scale of the target, collect scale of the edge;
@@ -1155,7 +1152,9 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
             // the entry is read together with the count (the list holds
             // work_cap entries, so the read stays inside it either way)
             const JtWork e = work[w];
-            if (w >= *work_count || e.task < 0) return;   // past the count, or per-XCD padding
+            // past the count, or per-XCD padding (both loads in flight together)
+            const int cnt = *work_count;
+            if ((w >= cnt) | (e.task < 0)) return;
             tix = e.task;
             slot = e.slot;
         } else {
@@ -1179,16 +1178,6 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
         F.lam_stride = lam_stride;
         F.scale_stride = st.scale;
         F.n_cliques = n_cliques;
-        // the message and the log-scales its finalize reads, loaded now so that
-        // their latency hides under the streaming (only the last block uses them)
-        JtMsg m;
-        FinScalars fs{0.0, 0.0, 0.0, 0.0};
-        if (it.msg >= 0) {
-            m = msgs[it.msg];   // uniform: scalar loads, in flight with the block's set-up
-#if JT_FS_EARLY
-            fs = load_fin_scalars(F, m, slot);
-#endif
-        }
         JtTask task;
         task.item = rec->item;
         task.g0 = rec->g0;
@@ -1242,9 +1231,12 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
                 last = L.last;
             }
             if (last) {
-#if !JT_FS_EARLY
-                fs = load_fin_scalars(F, m, slot);
-#endif
+                // the message record and its log-scales are loaded by the
+                // finalizing block only: loaded by every block at its start,
+                // the record's scalar registers (spilled under the pass's
+                // register pressure) put a wait on every block's set-up
+                const JtMsg m = msgs[it.msg];
+                const FinScalars fs = load_fin_scalars(F, m, slot);
                 if (wave_finalized(m)) {
                     if (threadIdx.x < JT_WAVE) wave_finalize_dist(F, m, fs, slot, threadIdx.x);
                 } else {
@@ -1281,7 +1273,8 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
     __shared__ int32_t ms_last[JT_MS];
     const int w = blockIdx.x;
     const JtWork e = work[w];
-    if (w >= *work_count || e.task < 0) return;
+    const int cnt = *work_count;
+    if ((w >= cnt) | (e.task < 0)) return;
     const JtChunk chk = chunks[e.slot];
     int ns = 0;
 #pragma unroll
