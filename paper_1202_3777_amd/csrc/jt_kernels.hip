@@ -1222,6 +1222,10 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
             // An acquire-release count (L2 write-back per block, L2 invalidate in
             // the last) gives the same results at a measured 1.6x the time of a
             // propagation, so the count stays relaxed.
+            // The message record is issued here, in flight with the count; only
+            // the finalizing block uses it (loaded at a block's start, its
+            // scalar registers would be held -- and spilled -- through the pass).
+            const JtMsg m = msgs[it.msg];
             wait_vm_stores();
             __syncthreads();
             bool last = true;
@@ -1231,11 +1235,6 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
                 last = L.last;
             }
             if (last) {
-                // the message record and its log-scales are loaded by the
-                // finalizing block only: loaded by every block at its start,
-                // the record's scalar registers (spilled under the pass's
-                // register pressure) put a wait on every block's set-up
-                const JtMsg m = msgs[it.msg];
                 const FinScalars fs = load_fin_scalars(F, m, slot);
                 if (wave_finalized(m)) {
                     if (threadIdx.x < JT_WAVE) wave_finalize_dist(F, m, fs, slot, threadIdx.x);
