@@ -108,7 +108,7 @@ def test_c4_batched_slots():
     run_case(inst, modes=("fused", "graph"))
 
 
-C4_FALLBACK_TUNING = {"target_blocks": 20480}
+C4_FALLBACK_TUNING = {"target_blocks": 10240}
 
 
 def bench_tuning(inst):
