@@ -164,6 +164,9 @@ typedef struct {
 // Up to JT_MS slots that read the same (evidence-free) source table in one
 // multi-slot distribute pass; unused entries are -1 (the used ones first).
 #define JT_MS 4
+// A level whose sets of JT_MS slots number fewer than one round of resident
+// multi-slot blocks (four per CU on a 256-CU GPU) is cut into sets of JT_MS / 2.
+#define JT_MULTI_ROUND 1024
 typedef struct {
     int32_t s[JT_MS];
 } JtChunk;

@@ -1050,7 +1050,8 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err, cons
             }
         }
         std::vector<Launch> L2;
-        const int64_t per_task_chunks = (P.n_slots + JT_MS - 1) / JT_MS;
+        // sets of JT_MS / 2 slots on short levels
+        const int64_t per_task_chunks = (P.n_slots + JT_MS / 2 - 1) / (JT_MS / 2);
         for (Launch l : P.fused) {
             if (l.count == 0) {
                 L2.push_back(l);
@@ -1424,23 +1425,34 @@ void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_va
                 order.push_back({-(16384 + (int64_t)(T.g1 - T.g0) * P.items[i].tpg * P.items[i].T), t});
             }
             std::stable_sort(order.begin(), order.end());
-            for (const auto &ot : order) {
-                const int32_t t = ot.second;
-                const int32_t c = P.items[P.tasks[l.begin + t].item].clique;
+            std::vector<std::pair<int64_t, std::vector<int32_t>>> sets;   // (order index, slots)
+            int64_t n_full = 0;
+            for (size_t oi = 0; oi < order.size(); ++oi) {
+                const int32_t c = P.items[P.tasks[l.begin + order[oi].second].item].clique;
                 std::vector<int32_t> sl;
                 if (share)
                     for (int32_t s = 0; s < n_active; ++s)
                         if (shared_src(s, c)) sl.push_back(s);
                 if (sl.empty()) continue;
+                n_full += ((int64_t)sl.size() + JT_MS - 1) / JT_MS;
+                sets.push_back({(int64_t)oi, std::move(sl)});
+            }
+            // sets of JT_MS slots, or of JT_MS / 2 when the level's sets of
+            // JT_MS would not fill one round of resident multi-slot blocks:
+            // more, shorter blocks then end a short level sooner
+            const size_t m = n_full < JT_MULTI_ROUND ? JT_MS / 2 : JT_MS;
+            for (const auto &ts : sets) {
+                const int32_t t = order[ts.first].second;
+                const std::vector<int32_t> &sl = ts.second;
                 const int32_t x = (int32_t)(std::min_element(load.begin(), load.end()) - load.begin());
-                for (size_t k0 = 0; k0 < sl.size(); k0 += JT_MS) {
+                for (size_t k0 = 0; k0 < sl.size(); k0 += m) {
                     JtChunk ch;
-                    for (int k = 0; k < JT_MS; ++k) ch.s[k] = k0 + k < sl.size() ? sl[k0 + k] : -1;
+                    for (size_t k = 0; k < JT_MS; ++k) ch.s[k] = (k < m && k0 + k < sl.size()) ? sl[k0 + k] : -1;
                     D.chunks[l.chunk_off + nch] = ch;
                     xl[x].push_back({t, (int32_t)nch});
                     ++nch;
                 }
-                load[x] += -ot.first * (int64_t)((sl.size() + JT_MS - 1) / JT_MS);
+                load[x] += -order[ts.first].first * (int64_t)((sl.size() + m - 1) / m);
             }
             size_t len = 0;
             for (const auto &v : xl) len = std::max(len, v.size());
