@@ -920,27 +920,91 @@ jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err, cons
         l.fork_after = fork;
         P.fused.push_back(l);
     };
+    // A pass multiplies up to JT_NG_REG ratio tables with indices held in
+    // registers; further ones are looked up tile by tile (a chain of
+    // dependent loads per tile).  A clique with more children therefore
+    // absorbs the messages of its earliest-finished children in pre-passes at
+    // earlier collect levels: JT_NG_REG messages each, the first reading the
+    // initial table (evidence entered), every one writing the collect table,
+    // each at a level after its children's and the previous pre-pass's and
+    // before the clique's own pass, which multiplies the rest and sums into
+    // the separator.  Only for tables of at most 2^22 entries: a pre-pass
+    // reads and writes the whole table once more, which on larger tables
+    // costs more than the lookups it saves (measured on a 2^23-entry root).
+    // (Not with lanes: a pre-pass would join them early.)
+    struct PrePass {
+        int32_t clique;
+        bool first;
+        std::vector<int32_t> children;
+    };
+    std::vector<std::vector<PrePass>> pre_at((size_t)P.height + 1);
+    std::vector<std::vector<int32_t>> final_children(nc);
+    std::vector<char> absorbed_before(nc, 0);
+    for (int32_t c = 0; c < nc; ++c) {
+        const std::vector<int32_t> &kids = P.cl[c].children;
+        final_children[c] = kids;
+        if ((int32_t)kids.size() <= JT_NG_REG || P.n_lanes > 0 || P.cl[c].size > (int64_t(1) << 22)) continue;
+        std::vector<int32_t> by_h = kids;
+        std::stable_sort(by_h.begin(), by_h.end(),
+                         [&](int32_t a, int32_t b) { return P.cl[a].height < P.cl[b].height; });
+        const size_t n_pre = kids.size() - JT_NG_REG;   // at most this many absorbed early
+        std::vector<char> early(nc, 0);
+        int32_t prev = -1;
+        for (size_t k0 = 0; k0 < n_pre; k0 += JT_NG_REG) {
+            const size_t k1 = std::min(n_pre, k0 + JT_NG_REG);
+            const int32_t level = std::max(prev + 1, P.cl[by_h[k1 - 1]].height + 1);
+            if (level >= P.cl[c].height) break;
+            PrePass pp;
+            pp.clique = c;
+            pp.first = prev < 0;
+            pp.children.assign(by_h.begin() + (std::ptrdiff_t)k0, by_h.begin() + (std::ptrdiff_t)k1);
+            for (int32_t ch : pp.children) early[ch] = 1;
+            pre_at[level].push_back(std::move(pp));
+            prev = level;
+        }
+        if (prev < 0) continue;
+        absorbed_before[c] = 1;
+        final_children[c].clear();
+        for (int32_t ch : kids)
+            if (!early[ch]) final_children[c].push_back(ch);
+    }
     for (int32_t h = 0; h <= P.height; ++h) {
         int64_t level_entries = 0;
         for (int32_t c : by_height[h]) level_entries += P.cl[c].size;
+        for (const PrePass &pp : pre_at[h]) level_entries += P.cl[pp.clique].size;
         const int64_t ge = group_entries_for(P, level_entries);
         const auto parts = split_lanes(by_height[h]);
         for (size_t li = 0; li < parts.size(); ++li) {
-        if (parts[li].empty()) continue;
+        std::vector<const PrePass *> pre_here;
+        for (const PrePass &pp : pre_at[h])
+            if ((size_t)(P.lane[pp.clique] + 1) == li) pre_here.push_back(&pp);
+        if (parts[li].empty() && pre_here.empty()) continue;
         const int32_t t0 = (int32_t)P.tasks.size(), m0 = (int32_t)P.msgs.size(), i0 = (int32_t)P.items.size();
         int64_t part_entries = 0;
         for (int32_t c : parts[li]) part_entries += P.cl[c].size;
+        for (const PrePass *pp : pre_here) part_entries += P.cl[pp->clique].size;
+        for (const PrePass *pp : pre_here) {
+            const CliqueInfo &C = P.cl[pp->clique];
+            std::vector<GatherSpec> gs;
+            for (int32_t ch : pp->children) gs.push_back({P.iedge[ch], false});
+            add_item(P, pp->clique, pp->first ? JT_SRC_INIT : JT_SRC_COLL, pp->first ? C.init_off : C.coll_off,
+                     JT_DST_COLL, C.coll_off, gs, -1, -1, 0, bytes, ge);
+        }
         std::vector<JtMsg> level_msgs;
         for (int32_t c : parts[li]) {
             const CliqueInfo &C = P.cl[c];
             std::vector<GatherSpec> gs;
-            for (int32_t ch : C.children) gs.push_back({P.iedge[ch], false});
+            for (int32_t ch : final_children[c]) gs.push_back({P.iedge[ch], false});
             const bool is_root = (c == P.root);
             const int32_t view = is_root ? C.total_view : C.parent_view;
             // partial size is known once the item's split is chosen: add the
             // item first with a placeholder, then patch its offset.
-            const int32_t it = add_item(P, c, JT_SRC_INIT, C.init_off, C.children.empty() ? JT_DST_NONE : JT_DST_COLL,
-                                        C.coll_off, gs, -1, view, 0, bytes, ge);
+            const int32_t it = absorbed_before[c]
+                                   ? add_item(P, c, JT_SRC_COLL, C.coll_off, JT_DST_COLL, C.coll_off, gs, -1, view, 0,
+                                              bytes, ge)
+                                   : add_item(P, c, JT_SRC_INIT, C.init_off,
+                                              C.children.empty() ? JT_DST_NONE : JT_DST_COLL, C.coll_off, gs, -1, view,
+                                              0, bytes, ge);
             const int64_t ss = P.views[view].ssize;
             const int64_t poff = add_partial(ss * item_nsplit(P, it));
             P.items[it].partial_off = poff;
@@ -1521,7 +1585,8 @@ void build_dynamic(const Plan &P, const std::vector<std::vector<int32_t>> &ev_va
                 for (int32_t s = 0; s < n_active; ++s) n += runs(s, c) ? 1 : 0;
                 if (share) n += 1;
                 D.collect_pairs += n;
-                if (n > 0) bytes += tb;                          // initial table
+                // the initial table once, or a pre-absorbed collect table per slot
+                if (n > 0) bytes += it.src_kind == JT_SRC_INIT ? tb : tb * n;
                 if (it.dst_kind != JT_DST_NONE) bytes += tb * n;  // absorbed tables
             } else {
                 // slots reading the shared source run in the level's

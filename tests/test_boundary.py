@@ -157,6 +157,13 @@ def _orient(parent, root):
     return np.array(bfs(root)[1]), ecc
 
 
+def _depth(parent, c):
+    d = 0
+    while parent[c] >= 0:
+        c, d = parent[c], d + 1
+    return d
+
+
 @pytest.mark.parametrize("name,kw", [("c1", {}), ("c4", dict(n_slots=1)), ("c2", dict(n_cliques=9)), ("c2", {}),
                                      ("c3", {})])
 def test_schedule_facts(name, kw):
@@ -177,12 +184,31 @@ def test_schedule_facts(name, kw):
     # initial table and writes its posterior, a clique with k children reads
     # its absorbed table k times and writes its posterior once (children in
     # the schedule's orientation)
+    # a clique with more than four children and at most 2^22 entries absorbs
+    # its earliest-finished children's messages four at a time in pre-passes
+    # at earlier collect levels (each after its children's level and the
+    # previous pre-pass, before the clique's own level): one more read and
+    # write of its table each
     kids = [np.count_nonzero(sparent == c) for c in range(inst.n_cliques)]
+    height = [0] * inst.n_cliques
+    order = sorted(range(inst.n_cliques), key=lambda c: -_depth(sparent, c))
+    for c in order:
+        if sparent[c] >= 0:
+            height[sparent[c]] = max(height[sparent[c]], height[c] + 1)
     exp = 0
     for c in range(inst.n_cliques):
         b = 4 * int(sizes[c])
         exp += b + (b if kids[c] else 0)
         exp += 2 * b if kids[c] == 0 else (kids[c] + 1) * b
+        if kids[c] > 4 and sizes[c] <= 1 << 22:
+            hs = sorted(height[x] for x in range(inst.n_cliques) if sparent[x] == c)
+            prev, n_pre = -1, kids[c] - 4
+            for k0 in range(0, n_pre, 4):
+                level = max(prev + 1, hs[min(n_pre, k0 + 4) - 1] + 1)
+                if level >= height[c]:
+                    break
+                exp += 2 * b
+                prev = level
     assert plan.query(jt.JT_Q_BYTES_FUSED) == exp
     # one-at-a-time: reset copy, marginalize + in-place scatter per message,
     # total + in-place normalize per clique
