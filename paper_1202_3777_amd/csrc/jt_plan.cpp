@@ -273,11 +273,28 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1, int64_t target_blocks) {
     const bool few = extra < tb / 2;
     const int64_t budget = few ? tb - extra : tb;
     const int64_t floor_ = P.tune.task_min > 0 ? P.tune.task_min : P.tune.group_min;
-    const int64_t target = std::max<int64_t>(floor_, few ? (entries + budget - 1) / budget : entries / budget);
-    for (int32_t i = i0; i < i1; ++i) {
+    int64_t target = std::max<int64_t>(floor_, few ? (entries + budget - 1) / budget : entries / budget);
+    // groups per block of item i for a target of entries per block
+    auto gpb_for = [&](int32_t i, int64_t tgt) {
         const int64_t ge = (int64_t)P.items[i].tpg * P.items[i].T * weight(i);   // work of a full group
-        const int64_t want = few ? (target + ge - 1) / ge : target / ge;
-        const int32_t gpb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(P.items[i].n_groups, want));
+        const int64_t want = few ? (tgt + ge - 1) / ge : tgt / ge;
+        return (int32_t)std::max<int64_t>(1, std::min<int64_t>(P.items[i].n_groups, want));
+    };
+    auto blocks_for = [&](int64_t tgt) {
+        int64_t n = 0;
+        for (int32_t i = i0; i < i1; ++i) n += (P.items[i].n_groups + gpb_for(i, tgt) - 1) / gpb_for(i, tgt);
+        return n * P.n_slots;
+    };
+    // The floor on a block's work can push a launch a little past its block
+    // target, and a few blocks past one round of resident blocks take about
+    // as long again: grow the blocks until the count fits (up to 2x over).
+    for (int k = 0; k < 8; ++k) {
+        const int64_t n = blocks_for(target);
+        if (n <= tb || n >= 2 * tb) break;
+        target = target * n / tb + 1;
+    }
+    for (int32_t i = i0; i < i1; ++i) {
+        const int32_t gpb = gpb_for(i, target);
         for (int32_t g0 = 0; g0 < P.items[i].n_groups; g0 += gpb) {
             P.items[i].n_tasks++;
             JtTask t;
