@@ -141,9 +141,8 @@ __device__ __forceinline__ void st_nt4(float *p, float a, float b, float c, floa
 }
 
 // One block's share of a pass: groups [task.g0, task.g1) of item `it`.
-// NT_SRC: the source table is streamed with non-temporal loads; off when the
-// launch reads the shared initial tables for several slots (those stay cached
-// for the other slots).
+// VEC: the lane layout of a tile (4 consecutive entries per lane as one
+// float4 when T % 4 == 0, else entries lane + 64 q).
 template <int VEC>
 __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task, int slot,
                                            const JtGather *__restrict__ gfirst,
