@@ -410,7 +410,8 @@ int32_t item_nsplit(const Plan &P, int32_t item) { return P.items[item].nsplit; 
 
 
 // Check, on the host, that every index the kernels derive from the plan
-// stays inside its buffer.  Run once per compiled tree; a failure here is a
+// stays inside its buffer and that the fused schedule's launches respect the
+// messages' dataflow.  Run once per compiled tree; a failure here is a
 // planner bug and is reported instead of launching anything.
 bool verify_plan(const Plan &P, std::string &why) {
     auto bad = [&](const std::string &m) {
@@ -601,10 +602,55 @@ bool verify_plan(const Plan &P, std::string &why) {
     }
     for (const Launch &l : P.plain)
         if (l.lane != -1 || l.join_before || l.fork_after) return bad("plain lanes");
+    // dataflow of the fused schedule, in launch order: a pass reads only
+    // messages finalized by an earlier launch; a clique's collect passes
+    // (pre-passes, then its own) run one per launch, the one reading its
+    // initial table first; a distribute pass reading the collect table runs
+    // after the last of them
+    {
+        std::map<int32_t, int32_t> by_sepc, by_sepd;   // separator table -> message writing it
+        for (size_t mi = 0; mi < P.msgs.size(); ++mi) {
+            const JtMsg &m = P.msgs[mi];
+            if (m.kind == JT_MSG_COLLECT) by_sepc[m.sepc_off] = (int32_t)mi;
+            if (m.kind == JT_MSG_DIST) by_sepd[m.sepd_off] = (int32_t)mi;
+        }
+        std::vector<int32_t> fin(P.msgs.size(), -1);        // launch finalizing each message
+        std::vector<int32_t> coll_last(P.n_cliques, -1);    // launch of a clique's latest collect pass
+        for (size_t li = 0; li < P.fused.size(); ++li) {
+            const Launch &l = P.fused[li];
+            if (l.is_pass != 1) continue;
+            std::set<int32_t> seen;
+            for (int32_t t = l.begin; t < l.begin + l.count; ++t) {
+                const int32_t i = P.tasks[t].item;
+                if (!seen.insert(i).second) continue;
+                const JtItem &it = P.items[i];
+                for (int32_t g = 0; g < it.n_gather; ++g) {
+                    const JtGather &G = P.gathers[it.gather_base + g];
+                    const std::map<int32_t, int32_t> &mp = G.src_clique < 0 ? by_sepd : by_sepc;
+                    const auto f = mp.find(G.sep_off);
+                    if (f == mp.end()) return bad("gathered table without a message");
+                    if (fin[f->second] < 0 || fin[f->second] >= (int32_t)li) return bad("message read before it is finalized");
+                }
+                if (l.collect && it.dst_kind == JT_DST_COLL) {
+                    const int32_t prev = coll_last[it.clique];
+                    if ((it.src_kind == JT_SRC_INIT) != (prev < 0)) return bad("collect passes out of order");
+                    if (prev >= (int32_t)li) return bad("two collect passes of a clique in one launch");
+                    coll_last[it.clique] = (int32_t)li;
+                }
+                if (!l.collect && it.src_kind == JT_SRC_COLL &&
+                    (coll_last[it.clique] < 0 || coll_last[it.clique] >= (int32_t)li))
+                    return bad("collect table read before it is complete");
+            }
+            for (int32_t i : seen)
+                if (P.items[i].msg >= 0) fin[P.items[i].msg] = (int32_t)li;
+        }
+    }
     return true;
 }
 
 }  // namespace
+
+bool check_plan(const Plan &P, std::string &why) { return verify_plan(P, why); }
 
 jt_status compile_plan(const jt_tree_desc *desc, Plan &P, std::string &err, const std::vector<FamilyReq> *families,
                        int64_t cpt_total) {

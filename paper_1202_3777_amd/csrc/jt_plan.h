@@ -175,6 +175,9 @@ void paper_mu_lists(const Plan &plan, const PaperPlan &pp, int32_t layout, int32
 // Build the plan; returns JT_OK or an error code with `err` filled in.
 // `families` (Bayesian-network trees only): the conditional tables to map
 // into their cliques; cpt_total their concatenated size.
+// The host-side checks compile_plan runs on every plan (index ranges, layouts
+// and the fused schedule's dataflow order); false with `why` on a failure.
+bool check_plan(const Plan &plan, std::string &why);
 jt_status compile_plan(const jt_tree_desc *desc, Plan &plan, std::string &err,
                        const std::vector<FamilyReq> *families = nullptr, int64_t cpt_total = 0);
 

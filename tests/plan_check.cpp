@@ -11,6 +11,7 @@
 //   * the collect sources point at the slot itself or at the shared slot;
 //   * the per-launch byte counts add up to the propagation's.
 // Prints "OK <summary>" or "FAIL <reason>" and exits non-zero on failure.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -66,6 +67,25 @@ int main(int argc, char **argv) {
     std::vector<std::vector<int32_t>> holders(nv);
     for (int32_t c = 0; c < nc; ++c)
         for (int64_t k = off[c]; k < off[c + 1]; ++k) holders[cv[k]].push_back(c);
+    // the dataflow check rejects a schedule whose launches are out of order:
+    // the collect sweep's last launch moved to the front reads messages no
+    // earlier launch finalized (single-slot plans: a batched plan's work
+    // lists are laid out in launch order, which the reordering would break
+    // first)
+    {
+        std::string why;
+        if (!jt::check_plan(P, why)) return fail("compiled plan rejected: " + why);
+        int32_t last_collect = -1;
+        for (size_t k = 0; k < P.fused.size(); ++k)
+            if (P.fused[k].collect && P.fused[k].count > 0) last_collect = (int32_t)k;
+        if (last_collect > 0 && !P.share) {
+            jt::Plan Q = P;
+            std::rotate(Q.fused.begin(), Q.fused.begin() + last_collect, Q.fused.begin() + last_collect + 1);
+            if (jt::check_plan(Q, why)) return fail("reordered schedule accepted");
+            if (why.find("before it is finalized") == std::string::npos && why.find("out of order") == std::string::npos)
+                return fail("reordered schedule rejected for another reason: " + why);
+        }
+    }
     long long n_multi_sets = 0, n_multi_pairs = 0, n_single = 0;
     for (int32_t na : {1, 2, (int32_t)std::max<long long>(1, ns / 2), (int32_t)ns}) {
         if (na < 1 || na > ns) continue;
