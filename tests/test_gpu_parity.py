@@ -139,6 +139,35 @@ def test_c4_full_batch_every_slot():
         compare(tree, plan, inst, s, plan.run(inst.potentials, *inst.evidence[s]), "c4/graph/all-slots")
 
 
+def test_c4_full_batch_repeats_bit_identical():
+    # the benchmark's configuration propagated again and again: graph replays
+    # and launch-by-launch propagations (one-slot and multi-slot launches on
+    # two streams, levels not joined in between) give the same bits every
+    # time -- a race between the streams would show as a difference
+    jt = _gpu()
+    import torch
+    inst = make_instance("c4", 0)
+    tree = jt.JunctionTree.from_instance(inst, tuning=bench_tuning(inst))
+    n, tot = inst.n_slots, int(tree.table_off[-1])
+
+    def run(mode):
+        tree.propagate(mode)
+        post = torch.empty(n * tot, dtype=torch.float32, device="cuda:0")
+        lz = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()   # allocated before the tree's stream writes them
+        jt.jt_read_out(tree.handle, 0, n, post.data_ptr(), lz.data_ptr())
+        torch.cuda.synchronize()
+        return post, lz
+
+    ref, rlz = run("graph")
+    assert bool(torch.isfinite(ref).all()) and bool((ref >= 0).all())
+    for k, mode in enumerate(("graph", "graph", "fused", "fused", "graph")):
+        print(f"[parity] c4 repeat {k} ({mode})", flush=True)
+        p, lz = run(mode)
+        assert torch.equal(p, ref) and torch.equal(lz, rlz), (k, mode)
+        del p, lz
+
+
 def test_c4_shared_edge_cases():
     # slots without any evidence (every collect message shared), a slot
     # observing one variable of the center clique, a batch where sharing is
