@@ -52,7 +52,9 @@ def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BU
         _run([HIPCC] + DEVICE_FLAGS + dfl + inc + ["-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     tmp = out + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    # librocprofiler-sdk-roctx: the host-side trace ranges around propagations and sweeps
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs +
+         ["-L", os.path.join(ROCM, "lib"), f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, out)
     if verbose:
         print("built", out)

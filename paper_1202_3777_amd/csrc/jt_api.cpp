@@ -2,6 +2,7 @@
 // device memory, evidence upload, the propagation schedules (level-fused,
 // captured graph, one message at a time) and read-out.
 #include <hip/hip_runtime_api.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -289,6 +290,19 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
     // node's first child on that node's stream) and the multi-slot nodes
     // form the branch.
     bool pending_join = false;
+    // host-side trace ranges (roctx) around the enqueue of each sweep of the
+    // fused schedule, "jt collect sweep" then "jt distribute sweep"; the open
+    // one is closed on every way out
+    struct SweepRange {
+        int open = -1;   // -1 none, 0 collect, 1 distribute
+        void to(int next) {
+            if (next == open) return;
+            if (open >= 0) roctxRangePop();
+            if (next >= 0) roctxRangePushA(next == 0 ? "jt collect sweep" : "jt distribute sweep");
+            open = next;
+        }
+        ~SweepRange() { to(-1); }
+    } sweep;
     const jt::Launch *deferred = nullptr;   // multi-slot launch waiting for its level's one-slot launch
     int deferred_grid = 0;
     auto launch_deferred = [&]() -> hipError_t {
@@ -310,6 +324,7 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
             if (e != hipSuccess) return hip_err(e, "side stream join");
         }
         hipStream_t s = l.lane >= 0 ? t->lane_stream[l.lane] : stream;
+        if (fused && l.is_pass == 1) sweep.to(l.collect ? 0 : 1);
         if (l.is_pass == 2) {
             e = jt_launch_plain_init(d, S, s);
         } else if (l.count > 0) {
@@ -345,6 +360,7 @@ jt_status enqueue(jt_tree t, const JtDev &d, const std::vector<jt::Launch> &L, i
         e = launch_deferred();
         if (e != hipSuccess) return hip_err(e, "kernel launch");
     }
+    sweep.to(-1);
     if (pending_join) {
         e = hipStreamWaitEvent(stream, t->side_join, 0);
         if (e != hipSuccess) return hip_err(e, "side stream join");
@@ -809,6 +825,8 @@ jt_status jt_propagate_n(jt_tree t, int32_t mode, int32_t n_active) {
     const bool paper = mode == JT_MODE_PAPER || mode == JT_MODE_PAPER_GRAPH;
     if (paper && !t->paper_ws) return set_err(JT_E_STATE, "paper schedule before jt_paper_bind");
     if (jt_status rc = prepare(t, n_active, mode == JT_MODE_FUSED || mode == JT_MODE_GRAPH)) return rc;
+    // host-side trace range (roctx) around one propagation's enqueue or graph launch
+    roctxRangePushA("jt_propagate");
     jt_status rc = JT_OK;
     if (mode == JT_MODE_PAPER)
         rc = enqueue_paper(t, n_active, t->stream);
@@ -820,6 +838,7 @@ jt_status jt_propagate_n(jt_tree t, int32_t mode, int32_t n_active) {
         rc = enqueue(t, t->dev, t->plan.plain, n_active, false, t->stream, nullptr);
     else
         rc = run_graph(t, n_active);
+    roctxRangePop();
     if (rc == JT_OK) {
         t->propagated = true;
         t->last_mode = mode;
