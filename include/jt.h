@@ -364,6 +364,9 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
  *   JT_Q_FUSED_LAUNCH_MULTI (arg = launch index: 1 for a multi-slot
  *     distribute launch, which runs on the handle's side stream beside the
  *     level's one-slot launch, 0 otherwise),
+ *   JT_Q_FUSED_LAUNCH_BLOCKS (arg = launch index: its blocks per evidence
+ *     set, i.e. its tasks; a launch over all slots runs that many per slot,
+ *     a listed one the (task, slot) pairs the evidence needs),
  *   JT_Q_ALG_BYTES (arg = slot count, 0 = all: the FP32 table bytes a fused
  *     propagation must move when every slot is computed on its own -- per
  *     clique and entry 12 B for a leaf (initial table read twice, posterior
@@ -403,6 +406,7 @@ jt_status jt_get_mu_lists(jt_tree t, int32_t child, int32_t side, int32_t *host_
 #define JT_Q_LAST_LAUNCH_BYTES 26
 #define JT_Q_ALG_BYTES 27
 #define JT_Q_FUSED_LAUNCH_MULTI 28
+#define JT_Q_FUSED_LAUNCH_BLOCKS 29
 jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out);
 
 /* Run one propagation with a HIP event pair around every kernel launch and

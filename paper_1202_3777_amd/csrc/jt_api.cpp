@@ -1094,6 +1094,7 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
         case JT_Q_FUSED_LAUNCH_KIND:
         case JT_Q_FUSED_LAUNCH_LANE:
         case JT_Q_FUSED_LAUNCH_MULTI:
+        case JT_Q_FUSED_LAUNCH_BLOCKS:
         case JT_Q_FUSED_LAUNCH_BYTES: {
             std::vector<const jt::Launch *> live;
             for (const jt::Launch &l : P.fused)
@@ -1102,7 +1103,8 @@ jt_status jt_query(jt_tree t, int32_t what, int64_t arg, int64_t *out) {
             *out = what == JT_Q_FUSED_LAUNCH_KIND    ? live[arg]->is_pass
                    : what == JT_Q_FUSED_LAUNCH_LANE  ? live[arg]->lane
                    : what == JT_Q_FUSED_LAUNCH_MULTI ? live[arg]->multi
-                                                     : live[arg]->bytes;
+                   : what == JT_Q_FUSED_LAUNCH_BLOCKS ? live[arg]->count
+                                                      : live[arg]->bytes;
             break;
         }
         case JT_Q_BYTES_LAST:

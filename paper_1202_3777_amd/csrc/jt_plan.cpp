@@ -285,9 +285,12 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1, int64_t target_blocks) {
         for (int32_t i = i0; i < i1; ++i) n += (P.items[i].n_groups + gpb_for(i, tgt) - 1) / gpb_for(i, tgt);
         return n * P.n_slots;
     };
-    // The floor on a block's work can push a launch a little past its block
-    // target, and a few blocks past one round of resident blocks take about
-    // as long again: grow the blocks until the count fits (up to 2x over).
+    // The floor on a block's work can push a launch past its block target,
+    // and the blocks of a second round of resident blocks take about as long
+    // again: when the count is up to 2x over, the work per block grows by the
+    // overshoot ratio (up to eight times).  A launch only a few blocks over
+    // keeps its blocks: doubling every block's work (the next step the
+    // groups allow) measured slower than the few extra blocks.
     for (int k = 0; k < 8; ++k) {
         const int64_t n = blocks_for(target);
         if (n <= tb || n >= 2 * tb) break;

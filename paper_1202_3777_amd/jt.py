@@ -66,6 +66,7 @@ JT_Q_COMPILED_TABLE_SIZE = 25
 JT_Q_LAST_LAUNCH_BYTES = 26
 JT_Q_ALG_BYTES = 27
 JT_Q_FUSED_LAUNCH_MULTI = 28
+JT_Q_FUSED_LAUNCH_BLOCKS = 29
 
 EXPORTED = ["jt_compile_index_maps", "jt_bind", "jt_set_evidence", "jt_propagate", "jt_propagate_n", "jt_marginal",
             "jt_marginals_all", "jt_read_out", "jt_paper_bytes", "jt_paper_bind", "jt_get_index_map", "jt_get_mu_lists", "jt_query", "jt_profile",

@@ -157,6 +157,21 @@ def _orient(parent, root):
     return np.array(bfs(root)[1]), ecc
 
 
+def test_launch_blocks():
+    # blocks per launch (per evidence set); on the large-clique tree the level
+    # whose work floor pushed it to 1,420 blocks against the default target
+    # of 1,280 (one round of resident blocks) is cut into larger blocks that
+    # fit one round, while launches only a few blocks over keep theirs
+    inst = make_instance("c2", 0)
+    plan = jt.JunctionTreePlan.from_instance(inst)
+    n = plan.query(jt.JT_Q_N_LAUNCHES_FUSED)
+    blocks = [plan.query(jt.JT_Q_FUSED_LAUNCH_BLOCKS, i) for i in range(n)]
+    assert all(b >= 1 for b in blocks)
+    assert not any(b > 1.02 * 1280 and b < 2 * 1280 for b in blocks), blocks
+    with pytest.raises(jt.JTError):
+        plan.query(jt.JT_Q_FUSED_LAUNCH_BLOCKS, n)
+
+
 def _depth(parent, c):
     d = 0
     while parent[c] >= 0:
