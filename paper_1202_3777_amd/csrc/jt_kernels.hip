@@ -1148,10 +1148,11 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
         const int w = blockIdx.x;
         int slot, tix;
         if (work) {
-            // the entry is read together with the count (the list holds
-            // work_cap entries, so the read stays inside it either way)
+            // the entry is read whether or not the block is past the count
+            // (the list holds work_cap >= grid entries, so the read stays
+            // inside it either way)
             const JtWork e = work[w];
-            // past the count, or per-XCD padding (both loads in flight together)
+            // past the count, or per-XCD padding
             const int cnt = *work_count;
             if ((w >= cnt) | (e.task < 0)) return;
             tix = e.task;
