@@ -157,6 +157,27 @@ def _orient(parent, root):
     return np.array(bfs(root)[1]), ecc
 
 
+def test_chained_prepasses():
+    # a hub with 14 children finishing at heights 0..6 (it is the tree's
+    # center, at height 7): its earliest children are absorbed in three
+    # chained pre-passes (levels 2, 4, 5; four, four and two messages), each
+    # a read and a write of the hub's table more than one pass would make
+    from shapes import hub_with_chains
+    inst, hub = hub_with_chains(0, n_slots=1)
+    plan = jt.JunctionTreePlan.from_instance(inst)
+    assert plan.query(jt.JT_Q_ROOT) == hub
+    sparent, _ = _orient(inst.parent, hub)
+    sizes = np.diff(inst.table_off)
+    kids = [np.count_nonzero(sparent == c) for c in range(inst.n_cliques)]
+    assert kids[hub] == 14
+    base = 0
+    for c in range(inst.n_cliques):
+        b = 4 * int(sizes[c])
+        base += b + (b if kids[c] else 0)
+        base += 2 * b if kids[c] == 0 else (kids[c] + 1) * b
+    assert plan.query(jt.JT_Q_BYTES_FUSED) == base + 3 * 2 * 4 * int(sizes[hub])
+
+
 def test_launch_blocks():
     # blocks per launch (per evidence set); on the large-clique tree the level
     # whose work floor pushed it to 1,420 blocks against the default target

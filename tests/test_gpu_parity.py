@@ -9,6 +9,8 @@ and held to 1e-4 (each such entry is a product of O(depth) rounded ratios
 and scales, a few hundred FP32 ulps at most).  The errors against FP64 are
 printed for every case.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -240,6 +242,18 @@ def test_odd_shapes():
     ]
     for inst in cases:
         run_case(inst)
+
+
+def test_hub_with_chained_prepasses():
+    # a hub whose 14 children finish at heights 0..6: its messages are
+    # absorbed in three chained pre-passes before the hub's own pass; four
+    # evidence sets batched (one evidence-free, so the hub's collect passes
+    # are shared by some sets and not by others), then each set alone
+    from shapes import hub_with_chains
+    inst, _ = hub_with_chains(0)
+    run_case(inst)
+    for ev in inst.evidence:
+        run_case(dataclasses.replace(inst, evidence=[ev]), modes=("fused", "plain"))
 
 
 def test_zero_evidence():
