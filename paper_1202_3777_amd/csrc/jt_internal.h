@@ -44,6 +44,9 @@
 #ifndef JT_WAVE_GROUP_TILES
 #define JT_WAVE_GROUP_TILES 16    /* output views with at most this many tiles per kept-outer configuration use wave groups */
 #endif
+#ifndef JT_PAIR_TILES
+#define JT_PAIR_TILES 1           /* tiles of at most JT_TILE_MAX / 2 entries are streamed two per wave load */
+#endif
 
 // One clique table seen through one separator (or through the empty
 // separator, for the table's total).
@@ -102,7 +105,8 @@ typedef struct {
     int32_t msg;                // message this pass produces and finalizes, -1 none
     int32_t wave_groups;        // 1: short groups (one kept-outer configuration each,
                                 // all its tiles), each streamed whole by one wave
-    int32_t pad;
+    int32_t pair;               // 1: T <= JT_TILE_MAX / 2 with 4-entry lanes, block
+                                // groups: a wave load covers two tiles, one per half-wave
 } JtItem;
 
 // A block's share of an item: groups [g0, g1), one after the other.

@@ -18,7 +18,8 @@
 // a quarter each; each lane holds the same 4 in-tile positions for every
 // tile, so its Jin values sit in registers, and the tile offsets and Jout
 // values of up to 64 tiles are fetched lane-parallel and read back with
-// readlane.  The segmented reduction is atomics-free and has a fixed order:
+// readlane (tiles of at most 128 entries go two to a wave, one per
+// half-wave).  The segmented reduction is atomics-free and has a fixed order:
 // a wave sums its tiles position by position in registers, the block adds
 // its four waves position by position in LDS, folds the positions of each
 // class (the separator configurations inside a tile) and writes one partial
@@ -88,6 +89,15 @@ struct TileBatch {
     float x[JT_UNROLL][4];
 };
 
+// The value that the lane owning this lane's tile of step uu holds in `v`:
+// chunk tile uu, or with PAIR chunk tile 2 uu + h for half-wave h.
+template <int PAIR>
+__device__ __forceinline__ int step_val(int v, int uu, int hl) {
+    if (!PAIR) return __builtin_amdgcn_readlane(v, uu);
+    const int v0 = __builtin_amdgcn_readlane(v, 2 * uu), v1 = __builtin_amdgcn_readlane(v, 2 * uu + 1);
+    return hl ? v1 : v0;
+}
+
 // Strides of the per-slot regions (values only, passed by value).
 struct PassStrides {
     int64_t coll, out, sep, partial, scale, ev_idx, ev_ent;
@@ -108,6 +118,16 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum of the four waves' position sums at in-tile position t, in a fixed
+// order (with PAIR each wave's two half-wave sums first).
+template <int PAIR>
+__device__ __forceinline__ float block_pos_sum(const PassLds &L, int t) {
+    if (!PAIR) return (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
+    constexpr int H = JT_TILE_MAX / 2;
+    return ((L.red[0][t] + L.red[0][H + t]) + (L.red[1][t] + L.red[1][H + t])) +
+           ((L.red[2][t] + L.red[2][H + t]) + (L.red[3][t] + L.red[3][H + t]));
 }
 
 // One wave folds the T position sums in `row` into the classes of the output
@@ -142,8 +162,12 @@ __device__ __forceinline__ void st_nt4(float *p, float a, float b, float c, floa
 
 // One block's share of a pass: groups [task.g0, task.g1) of item `it`.
 // VEC: the lane layout of a tile (4 consecutive entries per lane as one
-// float4 when T % 4 == 0, else entries lane + 64 q).
-template <int VEC>
+// float4 when T % 4 == 0, else entries lane + 64 q).  PAIR: tiles of at most
+// 128 entries are taken two at a time, one per half-wave (lanes 32 h + l
+// hold position 4 l + q, or l + 32 q, of the pair's tile h), so a load
+// instruction moves a whole wave's width; the two halves keep separate
+// position sums, added in a fixed order at the end of the group.
+template <int VEC, int PAIR>
 __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task, int slot,
                                            const JtGather *__restrict__ gfirst,
                                            const JtGather *__restrict__ gathers, const int32_t *__restrict__ meta,
@@ -157,12 +181,14 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     // group / tile bookkeeping and the metadata loads on the scalar unit
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / JT_WAVE);
     const int T = it.T;
+    const int hl = PAIR ? lane >> 5 : 0;   // the half-wave's tile of a pair
 
     int pos[4];
     bool valid[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        pos[q] = (VEC == 4) ? 4 * lane + q : lane + JT_WAVE * q;
+        const int pl = PAIR ? lane & 31 : lane;
+        pos[q] = (VEC == 4) ? 4 * pl + q : pl + (PAIR ? 32 : JT_WAVE) * q;
         valid[q] = pos[q] < T;
     }
 
@@ -223,22 +249,24 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     const int32_t rout_off = it.o_rout_tile;
     float *part = partial + (int64_t)slot * st.partial + it.partial_off;
 
-    // issue the loads of chunk tiles [u0, min(u0 + U, nt))
-    auto issue = [&](TileBatch &B, int u0, int nt, int my_o) {
+    // issue the loads of steps [u0, min(u0 + U, nst)) of a chunk of nt tiles
+    // (a step is one tile, or with PAIR two)
+    auto issue = [&](TileBatch &B, int u0, int nst, int nt, int my_o) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
             const int uu = u0 + u;
             B.o[u] = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) B.x[u][q] = 0.f;
-            if (uu < nt) {
+            if (uu < nst) {
                 // loaded even when evidence zeroes the tile (masked in
                 // consume), so the load does not wait for the evidence test
-                const int o = __builtin_amdgcn_readlane(my_o, uu);
+                const int o = step_val<PAIR>(my_o, uu, hl);
                 B.o[u] = o;
+                const bool tv = !PAIR || 2 * uu + hl < nt;
                 const float *base = src + (int64_t)o * T;
                 if (VEC == 4) {
-                    if (valid[0]) {
+                    if (valid[0] && tv) {
                         const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
                         B.x[u][0] = v4.x;
                         B.x[u][1] = v4.y;
@@ -248,17 +276,19 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (valid[q]) B.x[u][q] = base[pos[q]];
+                        if (valid[q] && tv) B.x[u][q] = base[pos[q]];
                 }
             }
         }
     };
-    // tile u of batch B (chunk tile uu): multiply in the gathers, mask,
-    // scale, store, accumulate
-    auto consume_one = [&](const TileBatch &B, int u, int uu, uint64_t zmask, const int (&my_jo)[JT_NG_REG],
-                           float (&acc)[4]) {
+    // entry u of batch B (step uu): multiply in the gathers, mask, scale,
+    // store, accumulate
+    auto consume_one = [&](const TileBatch &B, int u, int uu, int nt, uint64_t zmask,
+                           const int (&my_jo)[JT_NG_REG], float (&acc)[4]) {
         {
-            const bool zt = (zmask >> uu) & 1ull;   // outer evidence zeroes the whole tile
+            const int ti = PAIR ? 2 * uu + hl : uu;   // this lane's chunk tile
+            const bool tv = !PAIR || ti < nt;
+            const bool zt = (zmask >> ti) & 1ull;    // outer evidence zeroes the whole tile
             const int o = B.o[u];
             float v[4];
 #pragma unroll
@@ -266,7 +296,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) {
                 if (gg < ngr) {
-                    const int jo = __builtin_amdgcn_readlane(my_jo[gg], uu);
+                    const int jo = step_val<PAIR>(my_jo[gg], uu, hl);
                     if (gr[gg].in_lds) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) v[q] *= lds_ratio[gr[gg].off + jo + jin[gg][q]];
@@ -287,8 +317,8 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = (keep[q] && !zt) ? v[q] * scale : 0.f;
-            if (dst) {
+            for (int q = 0; q < 4; ++q) v[q] = (keep[q] && !zt && tv) ? v[q] * scale : 0.f;
+            if (dst && tv) {
                 float *b = dst + (int64_t)o * T;
                 if (VEC == 4) {
                     if (valid[0]) st_nt4(b + pos[0], v[0], v[1], v[2], v[3]);
@@ -302,12 +332,12 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             for (int q = 0; q < 4; ++q) acc[q] += v[q];
         }
     };
-    auto consume = [&](const TileBatch &B, int u0, int nt, uint64_t zmask, const int (&my_jo)[JT_NG_REG],
+    auto consume = [&](const TileBatch &B, int u0, int nst, int nt, uint64_t zmask, const int (&my_jo)[JT_NG_REG],
                        float (&acc)[4]) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
-            if (u0 + u >= nt) break;
-            consume_one(B, u, u0 + u, zmask, my_jo, acc);
+            if (u0 + u >= nst) break;
+            consume_one(B, u, u0 + u, nt, zmask, my_jo, acc);
         }
     };
 
@@ -334,7 +364,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
     };
     TileBatch A, B;
 
-    if (it.wave_groups) {
+    if (!PAIR && it.wave_groups) {
         // Short groups (one kept-outer configuration with its n_rout tiles
         // each): a wave streams a contiguous run of whole groups back to back,
         // metadata of 64 tiles at a time across group boundaries, and folds
@@ -370,7 +400,7 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
                     cur_g = gt;
                     cur_jk = __builtin_amdgcn_readlane(my_jk, uu);
                 }
-                consume_one(Bt, u, uu, zmask, my_jo, acc);
+                consume_one(Bt, u, uu, nt, zmask, my_jo, acc);
             }
         };
         bool staged = false;
@@ -395,15 +425,15 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             int my_jo[JT_NG_REG];
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) my_jo[gg] = (gg < ngr && live) ? meta[gr[gg].jout_off + my_o] : 0;
-            issue(A, 0, nt, my_o);
+            issue(A, 0, nt, nt, my_o);
             if (!staged) {
                 stage();
                 staged = true;
             }
             for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
-                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
+                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, nt, my_o);
                 consume_w(A, uq, nt, my_g, my_jk, zmask, my_jo);
-                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
+                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, nt, my_o);
                 if (uq + JT_UNROLL < nt) consume_w(B, uq + JT_UNROLL, nt, my_g, my_jk, zmask, my_jo);
             }
             cb += JT_WAVE;
@@ -444,17 +474,18 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
             int my_jo[JT_NG_REG];
 #pragma unroll
             for (int gg = 0; gg < JT_NG_REG; ++gg) my_jo[gg] = (gg < ngr && live) ? meta[gr[gg].jout_off + my_o] : 0;
-            issue(A, 0, nt, my_o);
+            const int nst = PAIR ? (nt + 1) >> 1 : nt;
+            issue(A, 0, nst, nt, my_o);
             if (!staged) {
                 stage();
                 staged = true;
             }
             // two batches of tiles in flight: load one while the other is consumed
-            for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
-                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
-                consume(A, uq, nt, zmask, my_jo, acc);
-                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
-                if (uq + JT_UNROLL < nt) consume(B, uq + JT_UNROLL, nt, zmask, my_jo, acc);
+            for (int uq = 0; uq < nst; uq += 2 * JT_UNROLL) {
+                if (uq + JT_UNROLL < nst) issue(B, uq + JT_UNROLL, nst, nt, my_o);
+                consume(A, uq, nst, nt, zmask, my_jo, acc);
+                if (uq + 2 * JT_UNROLL < nst) issue(A, uq + 2 * JT_UNROLL, nst, nt, my_o);
+                if (uq + JT_UNROLL < nst) consume(B, uq + JT_UNROLL, nst, nt, zmask, my_jo, acc);
             }
             cb += JT_WAVE;
         } while (cb < b);
@@ -464,9 +495,9 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
         // the output view folded in a fixed order into one partial row
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (valid[q]) L.red[wave][pos[q]] = acc[q];
+            if (valid[q]) L.red[wave][hl * (JT_TILE_MAX / 2) + pos[q]] = acc[q];
         __syncthreads();
-        for (int t = threadIdx.x; t < T; t += JT_BLOCK) L.pos[t] = (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
+        for (int t = threadIdx.x; t < T; t += JT_BLOCK) L.pos[t] = block_pos_sum<PAIR>(L, t);
         __syncthreads();
         if (wave == 0)
             fold_store(L.pos, L, it.o_n_cls, it.o_m_in, part + (int64_t)sp * it.o_ssize + meta[it.o_kout_j + k], lane);
@@ -480,8 +511,8 @@ __device__ __forceinline__ void pass_block(const JtItem &it, const JtTask &task,
 // (staged in LDS at k * ldsz) and scale, stored as the slot's posterior and
 // summed into the slot's partial rows -- in the same order, with the same
 // groups and folds, as the single-slot pass, so each slot's bits equal those
-// of its own pass.
-template <int VEC>
+// of its own pass (PAIR as in pass_block).
+template <int VEC, int PAIR>
 __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task, const int32_t *ms_slot, int ns,
                                            const JtGather &G, const int32_t *__restrict__ meta,
                                            const float *__restrict__ src, float *__restrict__ out,
@@ -493,11 +524,13 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
     const int lane = threadIdx.x & (JT_WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / JT_WAVE);
     const int T = it.T;
+    const int hl = PAIR ? lane >> 5 : 0;
     int pos[4];
     bool valid[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        pos[q] = (VEC == 4) ? 4 * lane + q : lane + JT_WAVE * q;
+        const int pl = PAIR ? lane & 31 : lane;
+        pos[q] = (VEC == 4) ? 4 * pl + q : pl + (PAIR ? 32 : JT_WAVE) * q;
         valid[q] = pos[q] < T;
     }
     int jin[4];
@@ -510,19 +543,20 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
     const bool has_out = it.out_view >= 0;
     const int32_t rout_off = it.o_rout_tile;
 
-    auto issue = [&](TileBatch &B, int u0, int nt, int my_o) {
+    auto issue = [&](TileBatch &B, int u0, int nst, int nt, int my_o) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
             const int uu = u0 + u;
             B.o[u] = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) B.x[u][q] = 0.f;
-            if (uu < nt) {
-                const int o = __builtin_amdgcn_readlane(my_o, uu);
+            if (uu < nst) {
+                const int o = step_val<PAIR>(my_o, uu, hl);
                 B.o[u] = o;
+                const bool tv = !PAIR || 2 * uu + hl < nt;
                 const float *base = src + (int64_t)o * T;
                 if (VEC == 4) {
-                    if (valid[0]) {
+                    if (valid[0] && tv) {
                         const float4 v4 = *reinterpret_cast<const float4 *>(base + pos[0]);
                         B.x[u][0] = v4.x;
                         B.x[u][1] = v4.y;
@@ -532,14 +566,15 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (valid[q]) B.x[u][q] = base[pos[q]];
+                        if (valid[q] && tv) B.x[u][q] = base[pos[q]];
                 }
             }
         }
     };
-    auto consume_one = [&](const TileBatch &B, int u, int uu, int my_jo, float (&acc)[JT_MS][4]) {
+    auto consume_one = [&](const TileBatch &B, int u, int uu, int nt, int my_jo, float (&acc)[JT_MS][4]) {
         const int o = B.o[u];
-        const int jo = __builtin_amdgcn_readlane(my_jo, uu);
+        const bool tv = !PAIR || 2 * uu + hl < nt;   // the lane's tile of the step exists
+        const int jo = step_val<PAIR>(my_jo, uu, hl);
 #pragma unroll
         for (int k = 0; k < JT_MS; ++k) {
             if (k >= ns) break;
@@ -551,7 +586,7 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
                 v[q] = B.x[u][q] * rk[jin[q]];
                 v[q] = v[q] * sk;
             }
-            if (has_dst) {
+            if (has_dst && tv) {
                 float *b = out + ms_dst[k] + (int64_t)o * T;
                 if (VEC == 4) {
                     if (valid[0]) st_nt4(b + pos[0], v[0], v[1], v[2], v[3]);
@@ -562,14 +597,14 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[k][q] += v[q];
+            for (int q = 0; q < 4; ++q) acc[k][q] += tv ? v[q] : 0.f;
         }
     };
-    auto consume = [&](const TileBatch &B, int u0, int nt, int my_jo, float (&acc)[JT_MS][4]) {
+    auto consume = [&](const TileBatch &B, int u0, int nst, int nt, int my_jo, float (&acc)[JT_MS][4]) {
 #pragma unroll
         for (int u = 0; u < JT_UNROLL; ++u) {
-            if (u0 + u >= nt) break;
-            consume_one(B, u, u0 + u, my_jo, acc);
+            if (u0 + u >= nst) break;
+            consume_one(B, u, u0 + u, nt, my_jo, acc);
         }
     };
     auto stage = [&]() {
@@ -593,7 +628,7 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[k][q] = 0.f;
 
-    if (it.wave_groups) {
+    if (!PAIR && it.wave_groups) {
         const int ngrp = task.g1 - task.g0;
         const int per = (ngrp + JT_WAVES_PER_BLOCK - 1) / JT_WAVES_PER_BLOCK;
         const int gw0 = task.g0 + min(ngrp, wave * per), gw1 = task.g0 + min(ngrp, wave * per + per);
@@ -626,7 +661,7 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
                     cur_g = gt;
                     cur_jk = __builtin_amdgcn_readlane(my_jk, uu);
                 }
-                consume_one(Bt, u, uu, my_jo, acc);
+                consume_one(Bt, u, uu, nt, my_jo, acc);
             }
         };
         bool staged = false;
@@ -643,15 +678,15 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
                 my_jk = meta[it.o_kout_j + my_g];
             }
             const int my_jo = live ? meta[G.jout_off + my_o] : 0;
-            issue(A, 0, nt, my_o);
+            issue(A, 0, nt, nt, my_o);
             if (!staged) {
                 stage();
                 staged = true;
             }
             for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
-                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
+                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, nt, my_o);
                 consume_w(A, uq, nt, my_g, my_jk, my_jo);
-                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
+                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, nt, my_o);
                 if (uq + JT_UNROLL < nt) consume_w(B, uq + JT_UNROLL, nt, my_g, my_jk, my_jo);
             }
             cb += JT_WAVE;
@@ -686,16 +721,17 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
             int my_o = 0;
             if (live) my_o = has_out ? tile_k + meta[rout_off + cb + lane] : cb + lane;
             const int my_jo = live ? meta[G.jout_off + my_o] : 0;
-            issue(A, 0, nt, my_o);
+            const int nst = PAIR ? (nt + 1) >> 1 : nt;
+            issue(A, 0, nst, nt, my_o);
             if (!staged) {
                 stage();
                 staged = true;
             }
-            for (int uq = 0; uq < nt; uq += 2 * JT_UNROLL) {
-                if (uq + JT_UNROLL < nt) issue(B, uq + JT_UNROLL, nt, my_o);
-                consume(A, uq, nt, my_jo, acc);
-                if (uq + 2 * JT_UNROLL < nt) issue(A, uq + 2 * JT_UNROLL, nt, my_o);
-                if (uq + JT_UNROLL < nt) consume(B, uq + JT_UNROLL, nt, my_jo, acc);
+            for (int uq = 0; uq < nst; uq += 2 * JT_UNROLL) {
+                if (uq + JT_UNROLL < nst) issue(B, uq + JT_UNROLL, nst, nt, my_o);
+                consume(A, uq, nst, nt, my_jo, acc);
+                if (uq + 2 * JT_UNROLL < nst) issue(A, uq + 2 * JT_UNROLL, nst, nt, my_o);
+                if (uq + JT_UNROLL < nst) consume(B, uq + JT_UNROLL, nst, nt, my_jo, acc);
             }
             cb += JT_WAVE;
         } while (cb < b);
@@ -707,10 +743,9 @@ __device__ __forceinline__ void pass_multi(const JtItem &it, const JtTask &task,
             if (kk >= ns) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (valid[q]) L.red[wave][pos[q]] = acc[kk][q];
+                if (valid[q]) L.red[wave][hl * (JT_TILE_MAX / 2) + pos[q]] = acc[kk][q];
             __syncthreads();
-            for (int t = threadIdx.x; t < T; t += JT_BLOCK)
-                posk[kk][t] = (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
+            for (int t = threadIdx.x; t < T; t += JT_BLOCK) posk[kk][t] = block_pos_sum<PAIR>(L, t);
             __syncthreads();
         }
         const int jk = meta[it.o_kout_j + k];
@@ -1199,12 +1234,15 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
         // evidence-free tables are read by many slots) and stored
         // non-temporally; one instance per lane layout keeps the kernel's
         // code small
-        if (it.vec == 4)
-            pass_block<4>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale,
-                          partial, st, lds_ratio, L);
+        if (it.pair)
+            pass_block<4, 1>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale,
+                             partial, st, lds_ratio, L);
+        else if (it.vec == 4)
+            pass_block<4, 0>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale,
+                             partial, st, lds_ratio, L);
         else
-            pass_block<1>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale,
-                          partial, st, lds_ratio, L);
+            pass_block<1, 0>(it, task, slot, rec->g, gathers, meta, ev_idx, ev_ent, src, dst, sep, cs_row, scale,
+                             partial, st, lds_ratio, L);
         if (it.msg >= 0) {
             int32_t *cnt = icnt + (int64_t)slot * icnt_stride + task.item;
             // Hand-off to the finalizing block, ordered by the hardware:
@@ -1300,12 +1338,15 @@ extern "C" __global__ __launch_bounds__(JT_BLOCK) __attribute__((amdgpu_waves_pe
                            ? init + it.src_off
                            : coll + (int64_t)csrc[(int64_t)chk.s[0] * csrc_stride + it.clique] * st.coll + it.src_off;
     __syncthreads();
-    if (it.vec == 4)
-        pass_multi<4>(it, task, ms_slot, ns, G, meta, src, out, sep, scale, partial, st, lds_ratio, L, posk, ms_part,
-                      ms_dst, ms_scl);
+    if (it.pair)
+        pass_multi<4, 1>(it, task, ms_slot, ns, G, meta, src, out, sep, scale, partial, st, lds_ratio, L, posk,
+                         ms_part, ms_dst, ms_scl);
+    else if (it.vec == 4)
+        pass_multi<4, 0>(it, task, ms_slot, ns, G, meta, src, out, sep, scale, partial, st, lds_ratio, L, posk,
+                         ms_part, ms_dst, ms_scl);
     else
-        pass_multi<1>(it, task, ms_slot, ns, G, meta, src, out, sep, scale, partial, st, lds_ratio, L, posk, ms_part,
-                      ms_dst, ms_scl);
+        pass_multi<1, 0>(it, task, ms_slot, ns, G, meta, src, out, sep, scale, partial, st, lds_ratio, L, posk,
+                         ms_part, ms_dst, ms_scl);
     if (it.msg < 0) return;
     const JtMsg m = msgs[it.msg];
     wait_vm_stores();   // this wave's partials are acknowledged (see jt_pass_kernel)

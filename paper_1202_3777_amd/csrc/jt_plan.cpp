@@ -400,6 +400,7 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         it.nsplit = 1;
         it.n_groups = (int32_t)((C.n_tiles + tpg - 1) / tpg);
     }
+    it.pair = (JT_PAIR_TILES && C.T <= JT_TILE_MAX / 2 && C.vec == 4 && !it.wave_groups) ? 1 : 0;
     P.items.push_back(it);
     const int32_t idx = (int32_t)P.items.size() - 1;
     // FP32 table bytes: shared initial tables are read once for all slots
@@ -483,6 +484,7 @@ bool verify_plan(const Plan &P, std::string &why) {
         if (it.tpg < 1 || it.nsplit < 1 || it.n_groups < 1) return bad("grouping");
         if (it.wave_groups && (it.out_view < 0 || it.nsplit != 1 || it.tpg != it.o_n_rout || it.tpg > JT_WAVE_GROUP_TILES))
             return bad("wave groups");
+        if (it.pair && (it.T > JT_TILE_MAX / 2 || it.vec != 4 || it.wave_groups)) return bad("paired tiles");
         if (it.out_view >= 0) {
             if (it.out_view >= (int32_t)P.views.size()) return bad("output view");
             const JtView &V = P.views[it.out_view];

@@ -47,13 +47,21 @@ DEFAULT_CANDIDATES: List[Dict[str, int]] = [
 ]
 
 
-def choose(candidates: Sequence[Dict[str, int]], timer: Callable[[Dict[str, int]], float]
-           ) -> Tuple[Dict[str, int], List[Tuple[Dict[str, int], float]]]:
-    """Time every candidate with `timer` (ms per propagation) and return the
-    fastest (the earliest listed among equals) with the whole table."""
-    table = [(dict(c), float(timer(c))) for c in candidates]
+def choose(candidates: Sequence[Dict[str, int]], timer: Callable[[Dict[str, int]], float],
+           finalists: int = 3, rounds: int = 3) -> Tuple[Dict[str, int], List[Tuple[Dict[str, int], float]]]:
+    """Time every candidate once with `timer` (ms per propagation), then time
+    the `finalists` fastest again, taking turns, `rounds` more times each, and
+    return the candidate with the lowest time seen (the earliest listed among
+    equals) with the table of every candidate's lowest time.  One timing of a
+    launch-bound schedule can be off by a percent or two, as much as the gaps
+    between the leading candidates; alternating repeats separate them."""
+    table = [[dict(c), float(timer(c))] for c in candidates]
+    top = sorted(range(len(table)), key=lambda i: (table[i][1], i))[:max(0, finalists)]
+    for _ in range(rounds):
+        for i in top:
+            table[i][1] = min(table[i][1], float(timer(table[i][0])))
     best = min(range(len(table)), key=lambda i: (table[i][1], i))
-    return table[best][0], table
+    return table[best][0], [(c, t) for c, t in table]
 
 
 def gpu_timer(inst, n_slots: Optional[int] = None, mode: str = "graph", steps: int = 10, warmup: int = 2,

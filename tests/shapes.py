@@ -42,3 +42,34 @@ def hub_with_chains(seed: int = 0, n_slots: int = 4):
     evidence = [(np.asarray(v, np.int32), np.asarray(s, np.int32)) for v, s in evidence[:n_slots]]
     inst = from_arrays(card, cliques, parent, evidence=evidence, seed=seed, name="hub-with-chains")
     return inst, 0
+
+
+def paired_tiles(seed: int = 0):
+    """A clique of 9 variables (cardinality 3 seven times, then 2, 2: its tile
+    is the last five variables, 108 entries, and it has 81 tiles) with 6
+    children of 4 variables each (2 shared, 2 fresh), and a grandchild under
+    the first child.  Tiles of at most 128 entries are streamed two to a
+    wave, and an odd tile count leaves a half-wave idle on the last step;
+    two of the children's separators are reduced in wave groups, the other
+    four in block groups.
+    Six evidence sets: none, an outer variable of the big clique (whole
+    tiles zeroed), an inner one (masked positions), both, child variables,
+    and the same as the first to share a multi-slot set."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    card = [3, 3, 3, 3, 3, 3, 3, 2, 2]
+    big = list(range(9))
+    cliques, parent = [big], [-1]
+    shared = [(0, 5), (1, 7), (2, 3), (4, 8), (0, 6), (3, 1)]
+    for a, b in shared:
+        f0, f1 = len(card), len(card) + 1
+        card += [int(rng.integers(2, 4)), int(rng.integers(2, 4))]
+        cliques.append([a, f0, b, f1])
+        parent.append(0)
+    g0 = len(card)
+    card += [2, 3]
+    cliques.append([cliques[1][1], g0, cliques[1][3], g0 + 1])
+    parent.append(1)
+    evidence = [([], []), ([1], [2]), ([6], [0]), ([0, 7], [1, 1]),
+                ([cliques[3][1], g0 + 1], [1, 2]), ([], [])]
+    inst = from_arrays(card, cliques, parent, evidence=evidence, seed=seed, name="paired-tiles")
+    return inst

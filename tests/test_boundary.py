@@ -322,6 +322,19 @@ def test_autotuner_picks_the_fastest():
     best, table = tune.choose(cands, lambda c: times[tuple(sorted(c.items()))])
     assert best == {"group_min": 4096}          # the earliest of the two fastest
     assert [t for _, t in table] == [3.0, 2.0, 2.0]
+    # a leading candidate timed slow once is timed again before the choice
+    seq = {(): [3.0, 3.0, 3.0, 3.0], (("group_min", 4096),): [2.0, 2.0, 2.0, 2.0],
+           (("target_blocks", 1024),): [2.5, 1.5, 1.6, 1.5]}
+    calls = []
+
+    def timer(c):
+        k = tuple(sorted(c.items()))
+        calls.append(k)
+        return seq[k][sum(1 for x in calls if x == k) - 1]
+    best, table = tune.choose(cands, timer, finalists=2, rounds=3)
+    assert best == {"target_blocks": 1024}
+    assert [t for _, t in table] == [3.0, 2.0, 1.5]
+    assert len(calls) == 3 + 2 * 3              # every candidate once, the two leaders thrice more
     for c in tune.DEFAULT_CANDIDATES:            # every default candidate compiles
         jt.JunctionTreePlan.from_instance(make_instance("c1", 0), tuning=c)
 

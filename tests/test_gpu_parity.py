@@ -256,6 +256,22 @@ def test_hub_with_chained_prepasses():
         run_case(dataclasses.replace(inst, evidence=[ev]), modes=("fused", "plain"))
 
 
+def test_paired_tiles():
+    # 108-entry tiles streamed two per wave load: 81 tiles (odd, a half-wave
+    # idles on each chunk's last step), evidence zeroing whole tiles and
+    # masking positions, six sets batched (two share multi-slot passes),
+    # then each set alone, and the batched bits equal the lone ones
+    from shapes import paired_tiles
+    inst = paired_tiles(0)
+    batched, _, _ = run_case(inst)
+    batched.propagate("fused")
+    for s, ev in enumerate(inst.evidence):
+        lone, _, _ = run_case(dataclasses.replace(inst, evidence=[ev]), modes=("plain", "fused"))
+        a, la = batched.marginals_all(s)
+        b, lb = lone.marginals_all(0)
+        assert np.array_equal(a, b) and la == lb, s
+
+
 def test_zero_evidence():
     jt = _gpu()
     card = [2, 2, 3]
