@@ -162,14 +162,16 @@ def ceilings():
 
 def measured_traffic(cfg, kernel, tuning=None):
     """HBM bytes per launch from the committed counter runs, or None when the
-    kernel source or the schedule's shape choices differ from those the
-    counters were taken with."""
-    from paper_1202_3777_amd.rocprof_summary import kernel_source_hash
+    kernel source, the planner's source or the schedule's shape choices
+    differ from those the counters were taken with."""
+    from paper_1202_3777_amd.rocprof_summary import kernel_source_hash, plan_source_hash
     f = TRAFFIC_FILE.format(cfg=cfg)
     if not os.path.exists(f):
         return None
     t = json.load(open(f))
     if t.get("source_sha256") != kernel_source_hash() or t.get("kernel") != kernel:
+        return None
+    if t.get("plan_sha256") != plan_source_hash():
         return None
     if (tuning or {}) != t.get("tuning", {}):
         return None

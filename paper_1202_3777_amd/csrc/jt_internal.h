@@ -42,7 +42,7 @@
 #define JT_LANES_ENABLED 0
 #endif
 #ifndef JT_WAVE_GROUP_TILES
-#define JT_WAVE_GROUP_TILES 16    /* output views with at most this many tiles per kept-outer configuration use wave groups */
+#define JT_WAVE_GROUP_TILES 28    /* output views with at most this many tiles per kept-outer configuration use wave groups */
 #endif
 #ifndef JT_PAIR_TILES
 #define JT_PAIR_TILES 1           /* tiles of at most JT_TILE_MAX / 2 entries are streamed two per wave load */
@@ -170,7 +170,9 @@ typedef struct {
 #define JT_MS 4
 // A level whose sets of JT_MS slots number fewer than one round of resident
 // multi-slot blocks (four per CU on a 256-CU GPU) is cut into sets of JT_MS / 2.
+#ifndef JT_MULTI_ROUND
 #define JT_MULTI_ROUND 1024
+#endif
 typedef struct {
     int32_t s[JT_MS];
 } JtChunk;

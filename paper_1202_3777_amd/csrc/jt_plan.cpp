@@ -310,6 +310,10 @@ void emit_tasks(Plan &P, int32_t i0, int32_t i1, int64_t target_blocks) {
     }
 }
 
+// An output view whose kept-outer configurations hold few tiles each is
+// reduced in wave groups (one wave streams a configuration's tiles whole).
+bool wave_group_view(int64_t n_rout) { return n_rout <= JT_WAVE_GROUP_TILES; }
+
 int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t dst_kind,
                  int64_t dst_off, const std::vector<GatherSpec> &gs, int32_t scale_clique,
                  int32_t out_view, int64_t partial_off, int64_t &bytes_acc, int64_t group_entries) {
@@ -375,7 +379,7 @@ int32_t add_item(Plan &P, int32_t c, int32_t src_kind, int64_t src_off, int32_t 
         // split partials (nsplit x |phi_S| floats) stay below 1/32 of the
         // table, or one separator table when that is larger
         const int64_t cap = std::max<int64_t>(V.ssize, std::min<int64_t>(kPartialMax, C.size / 32));
-        if (V.n_rout <= JT_WAVE_GROUP_TILES && V.n_kout > 1) {
+        if (wave_group_view(V.n_rout) && V.n_kout > 1) {
             // short groups: one per kept-outer configuration, a wave each,
             // streamed back to back (one partial row, nsplit = 1)
             it.wave_groups = 1;
@@ -482,7 +486,7 @@ bool verify_plan(const Plan &P, std::string &why) {
         }
         if (it.scale_clique >= P.n_cliques) return bad("scale clique");
         if (it.tpg < 1 || it.nsplit < 1 || it.n_groups < 1) return bad("grouping");
-        if (it.wave_groups && (it.out_view < 0 || it.nsplit != 1 || it.tpg != it.o_n_rout || it.tpg > JT_WAVE_GROUP_TILES))
+        if (it.wave_groups && (it.out_view < 0 || it.nsplit != 1 || it.tpg != it.o_n_rout || !wave_group_view(it.tpg)))
             return bad("wave groups");
         if (it.pair && (it.T > JT_TILE_MAX / 2 || it.vec != 4 || it.wave_groups)) return bad("paired tiles");
         if (it.out_view >= 0) {

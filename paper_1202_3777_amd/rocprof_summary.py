@@ -43,8 +43,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "jt_kernels.hip")
 
 
+PLAN_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("jt_plan.cpp", "jt_plan.h", "jt_internal.h")]
+
+
 def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def plan_source_hash() -> str:
+    """sha256 over the planner's sources: the schedule (launches, groups,
+    work lists) that the kernels run, and so the bytes they move."""
+    h = hashlib.sha256()
+    for f in PLAN_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def _csv(d, pattern):
@@ -129,6 +141,7 @@ def traffic(args):
     wb = sum(write) / len(write) * w_scale
     out = {"kernel": args.kernel, "kernels": [k.split("(")[0] for k in names],
            "source_sha256": kernel_source_hash(),
+           "plan_sha256": plan_source_hash(),
            "dispatches": [len(fetch), len(write)],
            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb,
            "copy_kernel": [cfk, cwk], "copy_bytes": args.copy_bytes,

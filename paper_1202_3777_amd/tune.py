@@ -18,6 +18,8 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "jt_kernels.hip")
+PLAN_SOURCES = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f)
+                for f in ("jt_plan.cpp", "jt_plan.h", "jt_internal.h")]
 
 # Candidates around the built-in defaults (group 8K..32K entries, 1280 blocks
 # per launch): one knob moved at a time, joint moves, and smaller least work
@@ -101,10 +103,12 @@ def autotune(inst, n_slots: Optional[int] = None, candidates: Optional[Sequence[
 def shape_key(inst, n_slots: Optional[int] = None, device_name: str = "") -> str:
     """Shape class of a tree for the tuning cache: what the shape choices
     depend on -- the tree's topology, every table and separator size, the
-    table layouts (tiles), the slot count, the GPU and the pass kernels'
-    source -- and nothing of the potentials or the evidence."""
+    table layouts (tiles), the slot count, the GPU, the pass kernels' source
+    and the planner's (which lays out the launches the choices cut) -- and
+    nothing of the potentials or the evidence."""
     h = hashlib.sha256()
-    h.update(open(KERNEL_SOURCE, "rb").read())
+    for f in [KERNEL_SOURCE] + PLAN_SOURCES:
+        h.update(open(f, "rb").read())
     for a in (inst.card, inst.clique_off, inst.clique_vars, inst.parent):
         h.update(a.tobytes())
     h.update(str(int(n_slots if n_slots is not None else max(1, inst.n_slots))).encode())

@@ -45,8 +45,8 @@ def hub_with_chains(seed: int = 0, n_slots: int = 4):
 
 
 def paired_tiles(seed: int = 0):
-    """A clique of 9 variables (cardinality 3 seven times, then 2, 2: its tile
-    is the last five variables, 108 entries, and it has 81 tiles) with 6
+    """A clique of 10 variables (cardinality 3 eight times, then 2, 2: its tile
+    is the last five variables, 108 entries, and it has 243 tiles) with 6
     children of 4 variables each (2 shared, 2 fresh), and a grandchild under
     the first child.  Tiles of at most 128 entries are streamed two to a
     wave, and an odd tile count leaves a half-wave idle on the last step;
@@ -56,10 +56,10 @@ def paired_tiles(seed: int = 0):
     tiles zeroed), an inner one (masked positions), both, child variables,
     and the same as the first to share a multi-slot set."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    card = [3, 3, 3, 3, 3, 3, 3, 2, 2]
-    big = list(range(9))
+    card = [3, 3, 3, 3, 3, 3, 3, 3, 2, 2]
+    big = list(range(10))
     cliques, parent = [big], [-1]
-    shared = [(0, 5), (1, 7), (2, 3), (4, 8), (0, 6), (3, 1)]
+    shared = [(0, 5), (1, 7), (2, 3), (4, 9), (0, 6), (3, 1)]
     for a, b in shared:
         f0, f1 = len(card), len(card) + 1
         card += [int(rng.integers(2, 4)), int(rng.integers(2, 4))]

@@ -257,7 +257,7 @@ def test_hub_with_chained_prepasses():
 
 
 def test_paired_tiles():
-    # 108-entry tiles streamed two per wave load: 81 tiles (odd, a half-wave
+    # 108-entry tiles streamed two per wave load: 243 tiles (odd, a half-wave
     # idles on each chunk's last step), evidence zeroing whole tiles and
     # masking positions, six sets batched (two share multi-slot passes),
     # then each set alone, and the batched bits equal the lone ones
