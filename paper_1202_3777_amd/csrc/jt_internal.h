@@ -24,11 +24,8 @@
 #define JT_LDS_RATIO_FLOATS 8192  /* at most 32 KiB of LDS for staged ratio tables */
 #define JT_FIN_LDS_FLOATS 64      /* smallest dynamic LDS of a pass launch */
 #define JT_FIN_STAGE_FLOATS 4096  /* separators up to this size are finalized through LDS */
-#ifndef JT_FIN_BATCH
-#define JT_FIN_BATCH 16           /* partial loads a finalize thread issues before using them */
-#endif
 #ifndef JT_UNROLL
-#define JT_UNROLL 3               /* tiles per batch; two batches in flight per wave */
+#define JT_UNROLL 2               /* tiles (paired: tile pairs) per batch; two batches in flight per wave */
 #endif
 #ifndef JT_MAX_LANES
 #define JT_MAX_LANES 4            /* streams the fused schedule could spread the root's subtrees over */
